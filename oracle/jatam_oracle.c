@@ -1,0 +1,602 @@
+/*
+ * jatam_oracle.c - plain, slow, obviously correct CPU oracle for JaTAM
+ * stochastic assembly and classification.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark, never by the product path.  It shares no
+ * code with the HIP library.  Every step follows the paper's definitions
+ * directly (citations per function); no blocking, fusion or bit tricks:
+ * cells are plain arrays, the frontier is a sorted list, options are found
+ * by scanning every oriented tile, the interaction rule is the matrix M.
+ */
+#include "jatam_oracle.h"
+
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw, */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of the  */
+/* S-P network with the two published multipliers, the key bumped by the    */
+/* two Weyl constants between rounds.  The paper's own generator (cuRAND    */
+/* XORWOW, §3) is replaced by this counter-based one so that every run of   */
+/* every genotype is reproducible from (seed, step, run, rng_id).           */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void jref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jenkins one-at-a-time hash (App. F.4), over unsigned bytes.               */
+/* ------------------------------------------------------------------------ */
+uint32_t jref_oaat(const uint8_t* bytes, int64_t n)
+{
+    uint32_t h = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        h += bytes[i];
+        h += h << 10;
+        h ^= h >> 6;
+    }
+    h += h << 3;
+    h ^= h >> 11;
+    h += h << 15;
+    return h;
+}
+
+uint64_t jref_default_rng_id(uint64_t genome, int t)
+{
+    return genome | ((uint64_t)(unsigned)t << 56);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shape hash made invariant under the dihedral group (§3.3 describes it   */
+/* for the four rotations; mirrors are added here): hash the cropped shape  */
+/* in each of the 8 orientations, each re-normalised to start at (0,0),    */
+/* listing occupied cells in (y, x) order as the bytes x, y; sort the 8     */
+/* hashes ascending and hash their 32 little-endian bytes again.            */
+/* ------------------------------------------------------------------------ */
+#define MAXG 64
+#define MAXW (MAXG + 1)
+
+/* (x', y') = (a*x + b*y, c*x + d*y), the 8 signed permutation matrices. */
+static const int D4_MAPS[8][4] = {
+    { 1, 0, 0, 1 }, { 0, -1, 1, 0 }, { -1, 0, 0, -1 }, { 0, 1, -1, 0 },
+    { -1, 0, 0, 1 }, { 1, 0, 0, -1 }, { 0, 1, 1, 0 }, { 0, -1, -1, 0 },
+};
+
+static int cmp_u32(const void* a, const void* b)
+{
+    uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+    return (x > y) - (x < y);
+}
+
+uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h)
+{
+    if (w <= 0 || h <= 0 || w > MAXW || h > MAXW)
+        return 0;
+    int n = 0;
+    for (int i = 0; i < w * h; ++i)
+        n += mask[i] != 0;
+    if (n == 0)
+        return 0;
+
+    uint32_t hashes[8];
+    static const int side = MAXW;
+    uint8_t* img = (uint8_t*)malloc((size_t)side * side);
+    uint8_t* bytes = (uint8_t*)malloc((size_t)2 * n);
+    for (int k = 0; k < 8; ++k) {
+        const int* T = D4_MAPS[k];
+        /* transformed coordinates, then shift so the minimum is 0 */
+        int minx = 1 << 30, miny = 1 << 30;
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x)
+                if (mask[y * w + x]) {
+                    int tx = T[0] * x + T[1] * y, ty = T[2] * x + T[3] * y;
+                    if (tx < minx) minx = tx;
+                    if (ty < miny) miny = ty;
+                }
+        memset(img, 0, (size_t)side * side);
+        for (int y = 0; y < h; ++y)
+            for (int x = 0; x < w; ++x)
+                if (mask[y * w + x]) {
+                    int tx = T[0] * x + T[1] * y - minx, ty = T[2] * x + T[3] * y - miny;
+                    img[ty * side + tx] = 1;
+                }
+        int m = 0;
+        for (int y = 0; y < side; ++y)
+            for (int x = 0; x < side; ++x)
+                if (img[y * side + x]) {
+                    bytes[m++] = (uint8_t)x;
+                    bytes[m++] = (uint8_t)y;
+                }
+        hashes[k] = jref_oaat(bytes, m);
+    }
+    free(img);
+    free(bytes);
+    qsort(hashes, 8, sizeof(uint32_t), cmp_u32);
+    uint8_t le[32];
+    for (int k = 0; k < 8; ++k)
+        for (int b = 0; b < 4; ++b)
+            le[4 * k + b] = (uint8_t)(hashes[k] >> (8 * b));
+    return jref_oaat(le, 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The tile model (§1.2, App. B.2, App. B.3).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Interaction matrix of App. B.2: M_ij = (1 - i mod 2) d(i, j+1)
+ * + (i mod 2) d(i, j-1); colours bond in adjacent pairs 1-2, 3-4, ...    */
+static int interacts(int i, int j)
+{
+    return (1 - i % 2) * (i == j + 1) + (i % 2) * (i == j - 1);
+}
+
+/* y grows downwards ("looking down on the configuration grid", App. B.3) */
+static const int DX[4] = { 0, 1, 0, -1 };
+static const int DY[4] = { -1, 0, 1, 0 };
+
+static int opposite(int d) { return (d + 2) % 4; }
+
+typedef struct {
+    int t, c, n;          /* n = 4t oriented tiles                          */
+    int tup[16][4];       /* colour oriented tile 4i+r shows on side d      */
+    int canon[16];        /* smallest oriented tile with the same tuple     */
+} model_t;
+
+static int log2_colours(int c)
+{
+    int b = 0;
+    while ((1 << b) < c)
+        ++b;
+    return b;
+}
+
+/* Colour of tile i on side d: tiles in order, seed first, each as its N, E,
+ * S, W colours, log2(c) bits each, most significant first (App. B.3). */
+static int colour_of(uint64_t genome, int t, int c, int i, int d)
+{
+    int b = log2_colours(c);
+    int shift = b * (4 * t - 1 - (4 * i + d));
+    return (int)((genome >> shift) & (uint64_t)(c - 1));
+}
+
+/* Oriented tiles: tile i turned clockwise by r quarter turns shows on side d
+ * the colour its side (d - r) mod 4 had; tiles rotate but never flip. */
+static void build_model(uint64_t genome, int t, int c, model_t* m)
+{
+    m->t = t;
+    m->c = c;
+    m->n = 4 * t;
+    for (int i = 0; i < t; ++i)
+        for (int r = 0; r < 4; ++r)
+            for (int d = 0; d < 4; ++d)
+                m->tup[4 * i + r][d] = colour_of(genome, t, c, i, (d - r + 4) % 4);
+    /* duplicate tile types and symmetric orientations are one tile (§3.2) */
+    for (int k = 0; k < m->n; ++k) {
+        m->canon[k] = k;
+        for (int k2 = 0; k2 < k; ++k2)
+            if (memcmp(m->tup[k2], m->tup[k], sizeof(m->tup[k])) == 0) {
+                m->canon[k] = m->canon[k2];
+                break;
+            }
+    }
+}
+
+/* The distinct tiles that can be placed next to a tile showing colour x,
+ * on the side of the new tile facing back (side `facing`).  Returns how
+ * many distinct tiles there are; *id receives one of them.            */
+static int options(const model_t* m, int x, int facing, int* id)
+{
+    int seen[16];
+    int count = 0;
+    for (int k = 0; k < m->n; ++k) {
+        if (!interacts(x, m->tup[k][facing]))
+            continue;
+        int ck = m->canon[k], dup = 0;
+        for (int s = 0; s < count; ++s)
+            dup |= seen[s] == ck;
+        if (!dup)
+            seen[count++] = ck;
+    }
+    if (count > 0)
+        *id = seen[0];
+    return count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One assembly run (§1.2, §3.2).                                            */
+/* ------------------------------------------------------------------------ */
+enum { EV_NONE = 0, EV_UNBOUND = 1, EV_AMBIG = 2 };
+
+typedef struct {
+    int G, W;                      /* W = G + 1: cells (x, y) in [0, G]^2  */
+    int16_t cell[MAXW * MAXW];     /* -1 empty, else the placed tile       */
+    int16_t pend[MAXW * MAXW];     /* -1 not on the frontier, else its tile */
+    int front[MAXW * MAXW];        /* frontier positions, ascending y*W+x  */
+    int nf;
+    int size;
+} grid_t;
+
+static int on_ring(const grid_t* g, int x, int y)
+{
+    return x == 0 || y == 0 || x == g->G || y == g->G;
+}
+
+static void frontier_insert(grid_t* g, int p)
+{
+    int i = g->nf;
+    while (i > 0 && g->front[i - 1] > p) {
+        g->front[i] = g->front[i - 1];
+        --i;
+    }
+    g->front[i] = p;
+    g->nf++;
+}
+
+static void frontier_remove_at(grid_t* g, int j)
+{
+    for (int i = j; i + 1 < g->nf; ++i)
+        g->front[i] = g->front[i + 1];
+    g->nf--;
+}
+
+/* Checks the empty neighbours of the tile just placed at p.  Any bondable
+ * site on the ring means the structure is not bounded by the box (App.
+ * B.2); a site whose occupied neighbours admit two distinct tiles is
+ * ambiguous (§3.2).  Otherwise a site with one admissible tile joins the
+ * frontier with that tile pending. */
+static int update(const model_t* m, grid_t* g, int p)
+{
+    int px = p % g->W, py = p / g->W;
+    int placed = g->cell[p];
+    int unbound = 0, ambiguous = 0;
+    for (int d = 0; d < 4; ++d) {
+        int qx = px + DX[d], qy = py + DY[d];
+        int q = qy * g->W + qx;
+        if (g->cell[q] >= 0)
+            continue;
+        int id = -1;
+        int k = options(m, m->tup[placed][d], opposite(d), &id);
+        if (k == 0)
+            continue;
+        if (on_ring(g, qx, qy))
+            unbound = 1;
+        else if (k >= 2 || (g->pend[q] >= 0 && g->pend[q] != id))
+            ambiguous = 1;
+        else if (g->pend[q] < 0) {
+            g->pend[q] = (int16_t)id;
+            frontier_insert(g, q);
+        }
+    }
+    return unbound ? EV_UNBOUND : ambiguous ? EV_AMBIG : EV_NONE;
+}
+
+typedef struct {
+    int event;
+    int steps;
+    int choice;     /* the frontier held >= 2 sites at some draw */
+} run_out_t;
+
+/* Grows one structure from the seed.  Each step draws one 32-bit word of
+ * the Philox stream keyed by the seed at counter (step/4, run, rng_id) and
+ * places the pending tile of the frontier site with rank floor(u*|F|/2^32)
+ * in row-major order.  trace, if not NULL, receives placed positions. */
+static run_out_t run_once(const model_t* m, grid_t* g, int run, uint64_t seed,
+                          uint64_t rng_id, int32_t* trace, int cap, int* ntrace)
+{
+    run_out_t out = { EV_NONE, 0, 0 };
+    int W = g->W;
+    for (int i = 0; i < W * W; ++i) {
+        g->cell[i] = -1;
+        g->pend[i] = -1;
+    }
+    g->nf = 0;
+    int centre = (g->G / 2) * W + g->G / 2;
+    g->cell[centre] = (int16_t)m->canon[0];
+    g->size = 1;
+    if (trace && *ntrace < cap)
+        trace[(*ntrace)++] = centre;
+    int ev = update(m, g, centre);
+    const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (;;) {
+        if (ev != EV_NONE)
+            break;
+        if (g->nf == 0)
+            break;
+        if (g->nf >= 2)
+            out.choice = 1;
+        uint32_t ctr[4] = { (uint32_t)out.steps >> 2, (uint32_t)run,
+                            (uint32_t)rng_id, (uint32_t)(rng_id >> 32) };
+        uint32_t words[4];
+        jref_philox4x32_10(ctr, key, words);
+        uint32_t u = words[out.steps & 3];
+        int j = (int)(((uint64_t)u * (uint64_t)g->nf) >> 32);
+        int p = g->front[j];
+        frontier_remove_at(g, j);
+        g->cell[p] = g->pend[p];
+        g->pend[p] = -1;
+        g->size++;
+        out.steps++;
+        if (trace && *ntrace < cap)
+            trace[(*ntrace)++] = p;
+        ev = update(m, g, p);
+    }
+    out.event = ev;
+    return out;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classification of one genotype (§3.2, §3.3).                              */
+/* ------------------------------------------------------------------------ */
+int jref_check_args(int t, int c, int grid, int runs)
+{
+    if (t < 1 || t > 4)
+        return JREF_E_INVALID_ARG;
+    if (c != 2 && c != 4 && c != 8 && c != 16)
+        return JREF_E_INVALID_ARG;
+    if (4 * t * log2_colours(c) > 64)
+        return JREF_E_INVALID_ARG;
+    if (grid < 8 || grid > MAXG || grid % 2 != 0)
+        return JREF_E_INVALID_ARG;
+    if (runs < 1 || runs > 64)
+        return JREF_E_INVALID_ARG;
+    return JREF_OK;
+}
+
+static int genome_fits(uint64_t genome, int t, int c)
+{
+    int bits = 4 * t * log2_colours(c);
+    return bits >= 64 || (genome >> bits) == 0;
+}
+
+/* Crop an occupancy mask of W*W cells to its bounding box (App. F.6) and
+ * hash the cropped shape. */
+static uint32_t hash_of_occupancy(const uint8_t* occ, int W)
+{
+    int minx = W, miny = W, maxx = -1, maxy = -1;
+    for (int y = 0; y < W; ++y)
+        for (int x = 0; x < W; ++x)
+            if (occ[y * W + x]) {
+                if (x < minx) minx = x;
+                if (y < miny) miny = y;
+                if (x > maxx) maxx = x;
+                if (y > maxy) maxy = y;
+            }
+    if (maxx < 0)
+        return 0;
+    int w = maxx - minx + 1, h = maxy - miny + 1;
+    uint8_t* mask = (uint8_t*)calloc((size_t)w * h, 1);
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x)
+            mask[y * w + x] = occ[(y + miny) * W + (x + minx)];
+    uint32_t hv = jref_shape_hash_d4(mask, w, h);
+    free(mask);
+    return hv;
+}
+
+static void occupancy_of(const grid_t* g, uint8_t* occ)
+{
+    for (int i = 0; i < g->W * g->W; ++i)
+        occ[i] = g->cell[i] >= 0;
+}
+
+static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome,
+                         uint64_t rng_id, int t, int c, int grid, int runs,
+                         uint64_t seed, jref_result_t* out, uint8_t* occ_out)
+{
+    if (jref_check_args(t, c, grid, runs) != JREF_OK || !genome_fits(genome, t, c))
+        return JREF_E_INVALID_ARG;
+    model_t m;
+    build_model(genome, t, c, &m);
+    g->G = grid;
+    g->W = grid + 1;
+    int cells = g->W * g->W;
+    int work = 0, size0 = 0;
+    for (int r = 0; r < runs; ++r) {
+        run_out_t ro = run_once(&m, g, r, seed, rng_id, NULL, 0, NULL);
+        work += ro.steps;
+        if (ro.event != EV_NONE) {
+            out->cls = ro.event == EV_UNBOUND ? JREF_UNBOUND : JREF_ND_SITE;
+            out->size = g->size;
+            out->hash = 0;
+            out->steps = work;
+            if (occ_out)
+                occupancy_of(g, occ_out);
+            return JREF_OK;
+        }
+        if (r == 0) {
+            occupancy_of(g, occ0);
+            size0 = g->size;
+            if (!ro.choice)  /* no draw ever chose: every run is this run */
+                break;
+        } else {
+            occupancy_of(g, occ);
+            if (memcmp(occ, occ0, (size_t)cells) != 0) {
+                out->cls = JREF_ND_RUNS;
+                out->size = g->size;
+                out->hash = 0;
+                out->steps = work;
+                if (occ_out)
+                    memcpy(occ_out, occ, (size_t)cells);
+                return JREF_OK;
+            }
+        }
+    }
+    out->cls = JREF_DET;
+    out->size = size0;
+    out->hash = hash_of_occupancy(occ0, g->W);
+    out->steps = work;
+    if (occ_out)
+        memcpy(occ_out, occ0, (size_t)cells);
+    return JREF_OK;
+}
+
+typedef struct {
+    grid_t g;
+    uint8_t occ0[MAXW * MAXW];
+    uint8_t occ[MAXW * MAXW];
+} workspace_t;
+
+int jref_classify_one(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
+                      int runs, uint64_t seed, jref_result_t* out, uint8_t* occ_out)
+{
+    workspace_t* ws = (workspace_t*)malloc(sizeof(workspace_t));
+    if (!ws)
+        return JREF_E_INVALID_ARG;
+    int rc = classify_with(&ws->g, ws->occ0, ws->occ, genome, rng_id, t, c, grid,
+                           runs, seed, out, occ_out);
+    free(ws);
+    return rc;
+}
+
+int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
+                   int run, uint64_t seed, int32_t* cells_out, int cap,
+                   int* event, int* choice)
+{
+    if (jref_check_args(t, c, grid, 1) != JREF_OK || !genome_fits(genome, t, c) || run < 0)
+        return JREF_E_INVALID_ARG;
+    workspace_t* ws = (workspace_t*)malloc(sizeof(workspace_t));
+    if (!ws)
+        return JREF_E_INVALID_ARG;
+    model_t m;
+    build_model(genome, t, c, &m);
+    ws->g.G = grid;
+    ws->g.W = grid + 1;
+    int n = 0;
+    run_out_t ro = run_once(&m, &ws->g, run, seed, rng_id, cells_out, cap, &n);
+    if (event)
+        *event = ro.event;
+    if (choice)
+        *choice = ro.choice;
+    free(ws);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Host thread pool: dynamic chunks of genotypes.                            */
+/* ------------------------------------------------------------------------ */
+enum { MODE_LIST = 0, MODE_RANGE = 1, MODE_ITEMS = 2 };
+
+typedef struct {
+    int mode;
+    const uint64_t* genomes;
+    const jref_item_t* items;
+    uint64_t first;
+    int64_t n;
+    int t, c, grid, runs;
+    uint64_t seed;
+    jref_result_t* out;
+    int64_t next;          /* next unclaimed index (atomic)  */
+    int error;             /* first error seen (atomic)      */
+} job_t;
+
+#define CHUNK 4096
+
+static void* worker(void* arg)
+{
+    job_t* job = (job_t*)arg;
+    workspace_t* ws = (workspace_t*)malloc(sizeof(workspace_t));
+    if (!ws) {
+        __atomic_store_n(&job->error, JREF_E_INVALID_ARG, __ATOMIC_RELAXED);
+        return NULL;
+    }
+    for (;;) {
+        int64_t begin = __atomic_fetch_add(&job->next, CHUNK, __ATOMIC_RELAXED);
+        if (begin >= job->n)
+            break;
+        int64_t end = begin + CHUNK < job->n ? begin + CHUNK : job->n;
+        for (int64_t i = begin; i < end; ++i) {
+            int rc;
+            if (job->mode == MODE_ITEMS) {
+                const jref_item_t* it = &job->items[i];
+                rc = classify_with(&ws->g, ws->occ0, ws->occ, it->genome, it->rng_id,
+                                   it->t, job->c, it->grid, job->runs, job->seed,
+                                   &job->out[i], NULL);
+            } else {
+                uint64_t g = job->mode == MODE_RANGE ? job->first + (uint64_t)i
+                                                     : job->genomes[i];
+                rc = classify_with(&ws->g, ws->occ0, ws->occ, g,
+                                   jref_default_rng_id(g, job->t), job->t, job->c,
+                                   job->grid, job->runs, job->seed, &job->out[i], NULL);
+            }
+            if (rc != JREF_OK)
+                __atomic_store_n(&job->error, rc, __ATOMIC_RELAXED);
+        }
+    }
+    free(ws);
+    return NULL;
+}
+
+static int run_job(job_t* job, int threads)
+{
+    if (job->n < 0)
+        return JREF_E_INVALID_ARG;
+    if (threads <= 0) {
+        long online = sysconf(_SC_NPROCESSORS_ONLN);
+        threads = online > 0 ? (int)online : 1;
+    }
+    if (threads > 256)
+        threads = 256;
+    job->next = 0;
+    job->error = JREF_OK;
+    pthread_t tid[256];
+    int started = 0;
+    for (int i = 1; i < threads; ++i)
+        if (pthread_create(&tid[started], NULL, worker, job) == 0)
+            ++started;
+    worker(job);
+    for (int i = 0; i < started; ++i)
+        pthread_join(tid[i], NULL);
+    return job->error;
+}
+
+int jref_classify(const uint64_t* genomes, int64_t n, int t, int c, int grid,
+                  int runs, uint64_t seed, jref_result_t* out, int threads)
+{
+    if (jref_check_args(t, c, grid, runs) != JREF_OK)
+        return JREF_E_INVALID_ARG;
+    job_t job = { MODE_LIST, genomes, NULL, 0, n, t, c, grid, runs, seed, out, 0, 0 };
+    return run_job(&job, threads);
+}
+
+int jref_classify_range(uint64_t first, int64_t n, int t, int c, int grid,
+                        int runs, uint64_t seed, jref_result_t* out, int threads)
+{
+    if (jref_check_args(t, c, grid, runs) != JREF_OK)
+        return JREF_E_INVALID_ARG;
+    job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out, 0, 0 };
+    return run_job(&job, threads);
+}
+
+int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
+                        uint64_t seed, jref_result_t* out, int threads)
+{
+    if (jref_check_args(1, c, 16, runs) != JREF_OK)
+        return JREF_E_INVALID_ARG;
+    job_t job = { MODE_ITEMS, NULL, items, 0, n, 1, c, 16, runs, seed, out, 0, 0 };
+    return run_job(&job, threads);
+}

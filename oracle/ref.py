@@ -1,0 +1,156 @@
+"""ctypes binding of the CPU oracle (libjatam_oracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark.  The product path never imports this module.
+Records are numpy structured arrays with the 16-byte layout
+{int32 cls, int32 size, uint32 hash, int32 steps}.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjatam_oracle.so")
+
+UNBOUND, ND_SITE, ND_RUNS, DET = 0, 1, 2, 3
+CLASS_NAMES = {UNBOUND: "UNBOUND", ND_SITE: "ND_SITE", ND_RUNS: "ND_RUNS", DET: "DET"}
+EV_NONE, EV_UNBOUND, EV_AMBIG = 0, 1, 2
+
+RECORD = np.dtype([("cls", "<i4"), ("size", "<i4"), ("hash", "<u4"), ("steps", "<i4")])
+ITEM = np.dtype([("genome", "<u8"), ("rng_id", "<u8"), ("t", "u1"), ("grid", "u1"),
+                 ("pad", "u1", (6,))])
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build as _build
+            _build.build()
+        L = ctypes.CDLL(LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.jref_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.jref_philox4x32_10.restype = None
+        L.jref_oaat.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.jref_oaat.restype = ctypes.c_uint32
+        L.jref_default_rng_id.argtypes = [ctypes.c_uint64, ctypes.c_int]
+        L.jref_default_rng_id.restype = ctypes.c_uint64
+        L.jref_shape_hash_d4.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+        L.jref_shape_hash_d4.restype = ctypes.c_uint32
+        L.jref_check_args.argtypes = [ctypes.c_int] * 4
+        L.jref_check_args.restype = ctypes.c_int
+        L.jref_classify_one.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+        L.jref_classify_one.restype = ctypes.c_int
+        L.jref_classify.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                    ctypes.c_void_p, ctypes.c_int]
+        L.jref_classify.restype = ctypes.c_int
+        L.jref_classify_range.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int]
+        L.jref_classify_range.restype = ctypes.c_int
+        L.jref_classify_items.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.c_int]
+        L.jref_classify_items.restype = ctypes.c_int
+        L.jref_trace_run.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                     ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.jref_trace_run.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key) -> tuple:
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().jref_philox4x32_10(c, k, o)
+    return tuple(int(v) for v in o)
+
+
+def oaat(data: bytes) -> int:
+    buf = ctypes.create_string_buffer(bytes(data), max(len(data), 1))
+    return int(lib().jref_oaat(buf, len(data)))
+
+
+def default_rng_id(genome: int, t: int) -> int:
+    return int(lib().jref_default_rng_id(genome, t))
+
+
+def shape_hash_d4(mask: np.ndarray) -> int:
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = m.shape
+    return int(lib().jref_shape_hash_d4(m.ctypes.data, w, h))
+
+
+def check_args(t: int, c: int, grid: int, runs: int) -> int:
+    return int(lib().jref_check_args(t, c, grid, runs))
+
+
+def classify_one(genome: int, t: int, c: int = 8, grid: int = 16, runs: int = 20,
+                 seed: int = 1, rng_id: int | None = None, with_occupancy: bool = False):
+    """Returns (cls, size, hash, steps) [, occupancy (G+1)x(G+1) uint8]."""
+    rid = default_rng_id(genome, t) if rng_id is None else rng_id
+    out = np.zeros(1, dtype=RECORD)
+    occ = np.zeros((grid + 1, grid + 1), dtype=np.uint8) if with_occupancy else None
+    rc = lib().jref_classify_one(genome, rid, t, c, grid, runs, seed, out.ctypes.data,
+                                 occ.ctypes.data if occ is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    rec = tuple(int(out[0][f]) for f in ("cls", "size", "hash", "steps"))
+    return (rec, occ) if with_occupancy else rec
+
+
+def classify(genomes: np.ndarray, t: int, c: int = 8, grid: int = 16, runs: int = 20,
+             seed: int = 1, threads: int = 0) -> np.ndarray:
+    g = np.ascontiguousarray(genomes, dtype=np.uint64)
+    out = np.zeros(g.shape[0], dtype=RECORD)
+    rc = lib().jref_classify(g.ctypes.data, g.shape[0], t, c, grid, runs, seed,
+                             out.ctypes.data, threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def classify_range(first: int, n: int, t: int, c: int = 8, grid: int = 16, runs: int = 20,
+                   seed: int = 1, threads: int = 0) -> np.ndarray:
+    out = np.zeros(n, dtype=RECORD)
+    rc = lib().jref_classify_range(first, n, t, c, grid, runs, seed, out.ctypes.data, threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def classify_items(items: np.ndarray, c: int = 8, runs: int = 20, seed: int = 1,
+                   threads: int = 0) -> np.ndarray:
+    it = np.ascontiguousarray(items, dtype=ITEM)
+    out = np.zeros(it.shape[0], dtype=RECORD)
+    rc = lib().jref_classify_items(it.ctypes.data, it.shape[0], c, runs, seed,
+                                   out.ctypes.data, threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def trace_run(genome: int, t: int, run: int, c: int = 8, grid: int = 16, seed: int = 1,
+              rng_id: int | None = None):
+    """Placed cells of one run in placement order as (x, y), plus event and choice."""
+    rid = default_rng_id(genome, t) if rng_id is None else rng_id
+    cap = (grid + 1) * (grid + 1)
+    cells = np.zeros(cap, dtype=np.int32)
+    ev, ch = ctypes.c_int(0), ctypes.c_int(0)
+    n = lib().jref_trace_run(genome, rid, t, c, grid, run, seed, cells.ctypes.data, cap,
+                             ctypes.byref(ev), ctypes.byref(ch))
+    if n < 0:
+        raise ValueError("oracle rejected arguments")
+    W = grid + 1
+    return [(int(p) % W, int(p) // W) for p in cells[:n]], int(ev.value), int(ch.value)

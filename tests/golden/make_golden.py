@@ -1,0 +1,58 @@
+"""Writes tests/golden/s28_digests.json and s18_digests.json.
+
+Calls only the CPU oracle: every expected value in those files comes from
+oracle/ (never from the HIP library).  Per 2^20-genotype slice of a space it
+stores the SHA-256 of the little-endian 16-byte records, the class tally and
+the summed steps.
+
+    python tests/golden/make_golden.py            # both files
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+from oracle import ref  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def slice_summary(recs):
+    return {
+        "sha256": hashlib.sha256(recs.tobytes()).hexdigest(),
+        "tally": [int(np.sum(recs["cls"] == k)) for k in range(4)],
+        "steps": int(recs["steps"].astype(np.int64).sum()),
+    }
+
+
+def make(t, grid, runs, seed, total, slice_n, path):
+    t0 = time.time()
+    slices = []
+    for first in range(0, total, slice_n):
+        n = min(slice_n, total - first)
+        recs = ref.classify_range(first, n, t, grid=grid, runs=runs, seed=seed)
+        s = slice_summary(recs)
+        s["first"] = first
+        s["n"] = n
+        slices.append(s)
+    doc = {
+        "space": f"S_{{{t},8}}", "t": t, "c": 8, "grid": grid, "runs": runs, "seed": seed,
+        "total": total, "slice": slice_n, "record": "int32 cls, int32 size, uint32 hash, int32 steps",
+        "writer": "tests/golden/make_golden.py (oracle only)",
+        "slices": slices,
+        "tally": [sum(s["tally"][k] for s in slices) for k in range(4)],
+        "steps": sum(s["steps"] for s in slices),
+    }
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(f"{path}: {time.time() - t0:.1f}s tally={doc['tally']}")
+
+
+if __name__ == "__main__":
+    make(1, 16, 20, 1, 4096, 4096, os.path.join(HERE, "s18_digests.json"))
+    make(2, 16, 20, 1, 1 << 24, 1 << 20, os.path.join(HERE, "s28_digests.json"))
