@@ -1,0 +1,117 @@
+/*
+ * jatam.h - C ABI of the MI355X (gfx950) JaTAM library.
+ *
+ * Stochastic assembly and classification of JaTAM genotypes (tile sets),
+ * the data-parallel hot path of Schroeder de Witt, "Biological Evolution and
+ * Genetic Algorithms - Exploring the Space of Abstract Tile Self-Assembly"
+ * (arXiv 2205.15311).
+ *
+ * Model (§1.2, App. B.2, App. B.3):
+ *   - A genotype is a set of t square tiles, tile 0 being the seed.  Its
+ *     genome holds the tiles in order, each as its N, E, S, W edge colours,
+ *     log2(c) bits per colour, most significant first: colour of tile i on
+ *     side d is (genome >> (b*(4t-1-(4i+d)))) & (c-1), b = log2(c).
+ *   - Colours bond in adjacent pairs 1-2, 3-4, ... (matrix M of App. B.2);
+ *     colour 0 and colour c-1, whose partner c does not exist (7 at c=8),
+ *     are inert.  Temperature 1: one bond suffices,
+ *     mismatched neighbours neither help nor hinder.  Tiles rotate by
+ *     quarter turns and never flip; duplicate and symmetric orientations
+ *     count as one tile (§3.2).
+ *   - A run grows the structure from the seed (unrotated) at the centre
+ *     (G/2, G/2) of a G x G grid.  The bounded box is the (G-1)-square
+ *     [1, G-1]^2; when a placement exposes a bondable site outside it the
+ *     genotype is UNBOUND (App. B.2, "unbounded by d").  Every empty site
+ *     next to the structure is checked isotropically: if the tiles that bond
+ *     to its occupied neighbours are not all one tile, the genotype is
+ *     non-deterministic (ND_SITE, §3.2).  Otherwise the run draws one 32-bit
+ *     word u of Philox4x32-10 (key = seed, counter = (step/4, run,
+ *     lo32(rng_id), hi32(rng_id)), word step%4) and places the pending tile
+ *     of the frontier site of rank floor(u*|F|/2^32) in row-major order.
+ *   - R runs are compared by occupancy without rotation (§3.2); the first
+ *     witness in run order decides (UNBOUND, ND_SITE, or ND_RUNS for a
+ *     different shape).  A run 0 that never had two frontier sites to choose
+ *     from used no random word, so all runs equal it and the rest are
+ *     skipped.  Otherwise the genotype is DET and its shape is hashed: crop
+ *     to the bounding box, one-at-a-time hash (App. F.4) of the occupied
+ *     cells' (x, y) bytes in row-major order for each of the 8 orientations
+ *     of the dihedral group, sort the 8 hashes, hash their 32 little-endian
+ *     bytes (§3.3 describes the four-rotation version).
+ *   - rng_id defaults to genome | (uint64)t << 56.
+ *
+ * Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ * stream); the caller synchronises.  All array arguments are DEVICE pointers
+ * owned by the caller; the library allocates nothing per call.  Every record
+ * is a pure function of (genome, t, c, grid, runs, seed, rng_id): it does not
+ * depend on the launch configuration, slice size or order of genotypes.
+ *
+ * Limits: 1 <= t <= 4, c in {2, 4, 8, 16} with 4*t*log2(c) <= 64, grid even
+ * in [8, 32], 1 <= runs <= 64, n >= 0.
+ */
+#ifndef JATAM_H
+#define JATAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One classification record, 16 bytes, written as one 16-byte store. */
+typedef struct {
+    int32_t  cls;    /* JATAM_UNBOUND .. JATAM_DET, or JATAM_INVALID           */
+    int32_t  size;   /* tiles in the deciding run when it ended (run 0 if DET) */
+    uint32_t hash;   /* D4-invariant shape hash if DET, else 0                 */
+    int32_t  steps;  /* placements summed over every run that was made         */
+} jatam_result_t;
+
+enum {
+    JATAM_INVALID = -1, /* record of a genome with bits set above 4*t*log2(c)   */
+    JATAM_UNBOUND = 0,  /* a bondable site appeared outside the bounded box     */
+    JATAM_ND_SITE = 1,  /* a site admitted two distinct tiles                   */
+    JATAM_ND_RUNS = 2,  /* a run ended in a shape different from run 0's        */
+    JATAM_DET = 3,      /* every run ended in run 0's shape                     */
+};
+
+enum {
+    JATAM_OK = 0,
+    JATAM_E_INVALID_ARG = -1, /* argument outside the limits above             */
+    JATAM_E_UNSUPPORTED = -2, /* valid model, not built for this grid size     */
+    JATAM_E_HIP = -3,         /* a HIP launch or runtime call failed           */
+};
+
+/*
+ * Classifies n genotypes given as an array (§3.2, §3.3).
+ *   genotypes  device, n x uint64, genome layout above; read once, coalesced
+ *   n          number of genotypes (0: no launch)
+ *   t, c       tiles per genotype and colour count
+ *   grid_limit G, the grid side (bounded box = (G-1)-square)
+ *   runs       R, independent runs per genotype
+ *   seed       Philox key
+ *   out        device, n x jatam_result_t, written once per genotype
+ *   stream     hipStream_t or NULL
+ * Returns JATAM_OK or a negative JATAM_E_* code; on error nothing is
+ * launched and out is untouched.  A genome with bits above its 4*t*log2(c)
+ * gets the record {JATAM_INVALID, 0, 0, 0}.
+ */
+int jatam_classify(const uint64_t* genotypes, int64_t n, int t, int c, int grid_limit,
+                   int runs, uint64_t seed, jatam_result_t* out, void* stream);
+
+/*
+ * Same, for the contiguous lexicographic range genome_i = first + i of the
+ * search space S_{t,c} (the enumerations of §4.1 and §4.3).  No input is
+ * read.  JATAM_E_INVALID_ARG if first + n exceeds c^(4t).
+ */
+int jatam_classify_range(uint64_t first, int64_t n, int t, int c, int grid_limit,
+                         int runs, uint64_t seed, jatam_result_t* out, void* stream);
+
+/* Static description of an error code. */
+const char* jatam_strerror(int code);
+
+/* Library ABI version (increments on any change to this header). */
+int jatam_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JATAM_H */

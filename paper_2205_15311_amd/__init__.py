@@ -1,0 +1,7 @@
+"""MI355X-native JaTAM assembly and classification (arXiv 2205.15311).
+
+The work is done by the HIP library libjatam.so (include/jatam.h); this
+package only binds it.
+"""
+from .jatam import (CLASS_NAMES, DET, INVALID, ND_RUNS, ND_SITE, UNBOUND, JatamError,  # noqa: F401
+                    abi_version, classify, classify_range, lib, records_to_numpy, strerror)

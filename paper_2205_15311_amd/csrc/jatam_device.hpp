@@ -1,0 +1,169 @@
+// jatam_device.hpp - device building blocks of JaTAM assembly on gfx950.
+//
+// Everything here is integer arithmetic in registers; nothing is shared with
+// the CPU oracle.  The pieces:
+//   philox4x32_10   counter-based generator (Salmon et al., SC'11) that
+//                   replaces the paper's cuRAND XORWOW (§3)
+//   oaat_*          Jenkins one-at-a-time hash (App. F.4), on unsigned bytes
+//   Model           a decoded genotype: tiles, their rotations, duplicate /
+//                   symmetric orientations merged (§3.2), and the bonding
+//                   options of every oriented tile (interaction rule of
+//                   App. B.2: colours bond in adjacent pairs 1-2, 3-4, ...)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jatam {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of the published S-P network; the key is bumped
+// by the two Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMul0 = 0xD2511F53u, kMul1 = 0xCD9E8D57u;
+    constexpr uint32_t kWeyl0 = 0x9E3779B9u, kWeyl1 = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi0 = __umulhi(kMul0, c0), lo0 = kMul0 * c0;
+        const uint32_t hi1 = __umulhi(kMul1, c2), lo1 = kMul1 * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kWeyl0;
+        k1 += kWeyl1;
+    }
+    return Words4{{c0, c1, c2, c3}};
+}
+
+// ---------------------------------------------------------------------------
+// One-at-a-time hash, split into its per-byte mix and its final avalanche.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t oaat_add(uint32_t h, uint32_t byte)
+{
+    h += byte;
+    h += h << 10;
+    h ^= h >> 6;
+    return h;
+}
+
+__device__ __forceinline__ uint32_t oaat_finish(uint32_t h)
+{
+    h += h << 3;
+    h ^= h >> 11;
+    h += h << 15;
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// A decoded genotype.
+//
+// Oriented tile k = 4*i + r is tile i turned clockwise by r quarter turns; it
+// is held as a 16-bit word of four nibbles, side d (N=0, E=1, S=2, W=3) in
+// bits 4d..4d+3.  For every side s the colours that all oriented tiles show
+// on s are packed as nibble k of side_cols[s], so one SWAR comparison finds
+// every oriented tile that shows a given colour there.  `reps` has bit 4k+3
+// set for each k that is the first oriented tile with its colour tuple:
+// duplicates and symmetric orientations collapse onto that representative.
+// ---------------------------------------------------------------------------
+struct Model {
+    uint32_t tile[4];        // tile i, nibble d = colour of side d
+    uint64_t side_cols[4];   // nibble k = colour oriented tile k shows on side s
+    uint64_t reps;           // bit 4k+3 set for representative oriented tiles
+    int c;                   // colour count
+};
+
+__device__ __forceinline__ uint32_t rotate_tile(uint32_t tile, int r)
+{
+    // side d shows the colour of side (d - r) mod 4: nibbles move up by r
+    const uint32_t s = 4u * (uint32_t)r;
+    return ((tile << s) | (tile >> ((16u - s) & 15u))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ Model build_model(uint64_t genome, int t, int bits, int c)
+{
+    Model m;
+    const uint32_t cmask = (uint32_t)c - 1u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t w = 0;
+        if (i < t) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int shift = bits * (4 * t - 1 - (4 * i + d));
+                w |= (uint32_t)((genome >> shift) & cmask) << (4 * d);
+            }
+        }
+        m.tile[i] = w;
+    }
+    m.side_cols[0] = m.side_cols[1] = m.side_cols[2] = m.side_cols[3] = 0;
+    uint32_t oriented[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            oriented[4 * i + r] = rotate_tile(m.tile[i], r);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            m.side_cols[s] |= (uint64_t)((oriented[k] >> (4 * s)) & 15u) << (4 * k);
+    uint64_t reps = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        bool first = k < 4 * t;
+#pragma unroll
+        for (int k2 = 0; k2 < k; ++k2)
+            first = first && (oriented[k2] != oriented[k]);
+        reps |= first ? (uint64_t)8u << (4 * k) : 0;
+    }
+    m.reps = reps;
+    m.c = c;
+    return m;
+}
+
+// Colour tuple of oriented tile k (k < 16).
+__device__ __forceinline__ uint32_t oriented_tile(const Model& m, int k)
+{
+    const int i = k >> 2;
+    uint32_t w = m.tile[0];
+    w = i == 1 ? m.tile[1] : w;
+    w = i == 2 ? m.tile[2] : w;
+    w = i == 3 ? m.tile[3] : w;
+    return rotate_tile(w, k & 3);
+}
+
+// Bonding options of the empty site next to oriented tile `a` in direction d:
+// the distinct representatives that show the partner of a's side-d colour on
+// their side facing back.  Returns min(count, 2) in bits 4..5 and the lowest
+// representative id in bits 0..3.
+__device__ __forceinline__ uint32_t site_options(const Model& m, uint32_t tuple, int d)
+{
+    const int x = (int)((tuple >> (4 * d)) & 15u);
+    // partner colour: 1<->2, 3<->4, ...; 0 and a last odd colour have none
+    const int p = ((x + 1) ^ 1) - 1;
+    if (p < 0 || p >= m.c)
+        return 0;
+    const uint64_t ones = 0x1111111111111111ull;
+    const uint64_t low3 = 0x7777777777777777ull;
+    const uint64_t v = m.side_cols[(d + 2) & 3] ^ (ones * (uint64_t)p);
+    // high bit of each nibble set iff the nibble is nonzero (no carries escape)
+    const uint64_t nonzero = v | ((v & low3) + low3);
+    const uint64_t match = ~nonzero & m.reps;
+    if (match == 0)
+        return 0;
+    const uint32_t id = (uint32_t)__builtin_ctzll(match) >> 2;
+    const uint32_t count = (match & (match - 1)) ? 2u : 1u;
+    return (count << 4) | id;
+}
+
+}  // namespace jatam

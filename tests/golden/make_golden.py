@@ -2,8 +2,8 @@
 
 Calls only the CPU oracle: every expected value in those files comes from
 oracle/ (never from the HIP library).  Per 2^20-genotype slice of a space it
-stores the SHA-256 of the little-endian 16-byte records, the class tally and
-the summed steps.
+stores the SHA-256 of the little-endian 16-byte records, the class tally, the
+summed steps and the summed size of DET genotypes.
 
     python tests/golden/make_golden.py            # both files
 """
@@ -27,6 +27,7 @@ def slice_summary(recs):
         "sha256": hashlib.sha256(recs.tobytes()).hexdigest(),
         "tally": [int(np.sum(recs["cls"] == k)) for k in range(4)],
         "steps": int(recs["steps"].astype(np.int64).sum()),
+        "det_size": int(recs["size"][recs["cls"] == 3].astype(np.int64).sum()),
     }
 
 
@@ -47,6 +48,7 @@ def make(t, grid, runs, seed, total, slice_n, path):
         "slices": slices,
         "tally": [sum(s["tally"][k] for s in slices) for k in range(4)],
         "steps": sum(s["steps"] for s in slices),
+        "det_size": sum(s["det_size"] for s in slices),
     }
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)

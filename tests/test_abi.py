@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/jatam.h declares, and rejects bad arguments before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(jatam_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2205_15311_amd import jatam
+    if not os.path.exists(jatam.LIB_PATH):
+        pytest.fail("libjatam.so is not built (run __graft_entry__.build())")
+    return jatam.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "jatam_classify" in names and "jatam_classify_range" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_strerror(lib):
+    from paper_2205_15311_amd import jatam
+    assert jatam.abi_version() >= 1
+    for code in (0, -1, -2, -3, -99):
+        assert isinstance(jatam.strerror(code), str)
+
+
+@pytest.mark.parametrize("t,c,grid,runs", [(0, 8, 16, 20), (5, 8, 16, 20), (2, 3, 16, 20),
+                                           (2, 8, 15, 20), (2, 8, 6, 20), (2, 8, 66, 20),
+                                           (2, 8, 16, 0), (2, 8, 16, 65), (4, 32, 16, 1)])
+def test_invalid_arguments_rejected(lib, t, c, grid, runs):
+    out = ctypes.create_string_buffer(16)
+    g = ctypes.c_uint64(0)
+    assert lib.jatam_classify(ctypes.addressof(g), 1, t, c, grid, runs, 1, out, None) == -1
+    assert lib.jatam_classify_range(0, 1, t, c, grid, runs, 1, out, None) == -1
+
+
+def test_unsupported_grid(lib):
+    out = ctypes.create_string_buffer(16)
+    assert lib.jatam_classify_range(0, 1, 2, 8, 64, 20, 1, out, None) == -2
+
+
+def test_range_beyond_space_rejected(lib):
+    out = ctypes.create_string_buffer(16)
+    assert lib.jatam_classify_range((1 << 24) - 1, 2, 2, 8, 16, 20, 1, out, None) == -1
+    assert lib.jatam_classify_range(0, -1, 2, 8, 16, 20, 1, out, None) == -1
+    # null buffers with n > 0
+    assert lib.jatam_classify_range(0, 1, 2, 8, 16, 20, 1, None, None) == -1
+    assert lib.jatam_classify(None, 1, 2, 8, 16, 20, 1, out, None) == -1
+
+
+def test_empty_call_launches_nothing(lib):
+    assert lib.jatam_classify(None, 0, 2, 8, 16, 20, 1, None, None) == 0
+    assert lib.jatam_classify_range(0, 0, 2, 8, 16, 20, 1, None, None) == 0
