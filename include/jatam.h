@@ -104,6 +104,83 @@ int jatam_classify(const uint64_t* genotypes, int64_t n, int t, int c, int grid_
 int jatam_classify_range(uint64_t first, int64_t n, int t, int c, int grid_limit,
                          int runs, uint64_t seed, jatam_result_t* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Pipelined ("batched") classification.
+ *
+ * Same records as jatam_classify, produced by a pipeline that keeps lanes
+ * busy: a screen of every genotype's seed, a device queue of first runs
+ * drained by persistent waves, and the repeat runs of deterministic
+ * candidates ordered by their exact cost (run-0 size), one lane per run (the
+ * batching and asynchronous execution of §3.4, and the "as many assembly
+ * processes in parallel" optimisation suggested in §4.1).  The queues live in
+ * a workspace created once; no call allocates.  Calls sharing one workspace
+ * must be serialised (same stream); calls on different workspaces may run
+ * concurrently.
+ * ------------------------------------------------------------------------ */
+
+/* One genotype of a mixed stream: its own tile count, grid and RNG stream. */
+typedef struct {
+    uint64_t genome;   /* genome layout above, t tiles                        */
+    uint64_t rng_id;   /* Philox stream id (the default is genome | t << 56)  */
+    uint8_t  t;        /* 1..4                                                 */
+    uint8_t  grid;     /* G, even, 8..32                                       */
+    uint8_t  pad[6];
+} jatam_item_t;        /* 24 bytes */
+
+typedef struct jatam_batch jatam_batch_t;
+
+/*
+ * Creates a workspace for calls of up to max_n (1 <= max_n < 2^32) genotypes
+ * on the current HIP device: 28 bytes of device memory per genotype plus a
+ * few KiB.  Blocks until the workspace is initialised.  *batch receives the
+ * handle; JATAM_E_HIP if device memory runs out.
+ */
+int jatam_batch_create(int64_t max_n, jatam_batch_t** batch);
+
+/* Frees a workspace (NULL is accepted).  Synchronises its device. */
+int jatam_batch_destroy(jatam_batch_t* batch);
+
+/*
+ * Pipelined equivalents of jatam_classify / jatam_classify_range, and a
+ * mixed-item call where every genotype carries its own t, grid and rng_id.
+ *   batch  workspace from jatam_batch_create, same device, n <= its max_n
+ *   tally  NULL, or device uint64[4] to which the number of UNBOUND,
+ *          ND_SITE, ND_RUNS and DET records is ADDED (the caller zeroes it)
+ * Other arguments and errors as for jatam_classify.  Items with t, grid or
+ * genome outside the limits get JATAM_INVALID records.
+ */
+int jatam_batch_classify(jatam_batch_t* batch, const uint64_t* genotypes, int64_t n, int t,
+                         int c, int grid_limit, int runs, uint64_t seed, jatam_result_t* out,
+                         uint64_t* tally, void* stream);
+int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, int t, int c,
+                               int grid_limit, int runs, uint64_t seed, jatam_result_t* out,
+                               uint64_t* tally, void* stream);
+int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, int64_t n,
+                               int c, int runs, uint64_t seed, jatam_result_t* out,
+                               uint64_t* tally, void* stream);
+
+/*
+ * Tuning of the first-run stage: a wave refills its idle lanes (screening
+ * new genotypes and starting their first runs) once at least idle_lanes of
+ * its 64 lanes are idle (1..64; default 24).  Records never depend on it.
+ */
+int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
+
+/*
+ * Timing hook of the pipeline, for measurement.  While enabled, every call on
+ * `batch` records HIP events on its stream around each stage (one event pair
+ * per stage and call; enabling or disabling synchronises the device and
+ * forgets earlier events).  jatam_batch_stage_times waits for the recorded
+ * calls and writes, per stage s < max_stages, the summed duration in ms over
+ * those calls to ms[s] and, if calls is not NULL, how many calls ran it to
+ * calls[s]; it returns the number of stages written.  Stage names:
+ * jatam_batch_stage_name (0 first runs, 1 size sort, 2 repeat runs for
+ * G <= 16; 3-5 the same for G <= 32).
+ */
+int jatam_batch_set_timing(jatam_batch_t* batch, int enable);
+int jatam_batch_stage_times(jatam_batch_t* batch, double* ms, int* calls, int max_stages);
+const char* jatam_batch_stage_name(int stage);
+
 /* Static description of an error code. */
 const char* jatam_strerror(int code);
 

@@ -404,9 +404,16 @@ static void occupancy_of(const grid_t* g, uint8_t* occ)
         occ[i] = g->cell[i] >= 0;
 }
 
+typedef struct {
+    int steps;
+    int event;
+    int choice;
+} run0_info_t;
+
 static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome,
                          uint64_t rng_id, int t, int c, int grid, int runs,
-                         uint64_t seed, jref_result_t* out, uint8_t* occ_out)
+                         uint64_t seed, jref_result_t* out, uint8_t* occ_out,
+                         run0_info_t* info0)
 {
     if (jref_check_args(t, c, grid, runs) != JREF_OK || !genome_fits(genome, t, c))
         return JREF_E_INVALID_ARG;
@@ -419,6 +426,11 @@ static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome
     for (int r = 0; r < runs; ++r) {
         run_out_t ro = run_once(&m, g, r, seed, rng_id, NULL, 0, NULL);
         work += ro.steps;
+        if (r == 0 && info0) {
+            info0->steps = ro.steps;
+            info0->event = ro.event;
+            info0->choice = ro.choice;
+        }
         if (ro.event != EV_NONE) {
             out->cls = ro.event == EV_UNBOUND ? JREF_UNBOUND : JREF_ND_SITE;
             out->size = g->size;
@@ -468,7 +480,7 @@ int jref_classify_one(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
     if (!ws)
         return JREF_E_INVALID_ARG;
     int rc = classify_with(&ws->g, ws->occ0, ws->occ, genome, rng_id, t, c, grid,
-                           runs, seed, out, occ_out);
+                           runs, seed, out, occ_out, NULL);
     free(ws);
     return rc;
 }
@@ -510,6 +522,9 @@ typedef struct {
     int t, c, grid, runs;
     uint64_t seed;
     jref_result_t* out;
+    int32_t* run0_steps;   /* optional run-0 detail          */
+    int8_t* run0_event;
+    int8_t* run0_choice;
     int64_t next;          /* next unclaimed index (atomic)  */
     int error;             /* first error seen (atomic)      */
 } job_t;
@@ -535,13 +550,20 @@ static void* worker(void* arg)
                 const jref_item_t* it = &job->items[i];
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, it->genome, it->rng_id,
                                    it->t, job->c, it->grid, job->runs, job->seed,
-                                   &job->out[i], NULL);
+                                   &job->out[i], NULL, NULL);
             } else {
                 uint64_t g = job->mode == MODE_RANGE ? job->first + (uint64_t)i
                                                      : job->genomes[i];
+                run0_info_t info = { 0, 0, 0 };
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, g,
                                    jref_default_rng_id(g, job->t), job->t, job->c,
-                                   job->grid, job->runs, job->seed, &job->out[i], NULL);
+                                   job->grid, job->runs, job->seed, &job->out[i], NULL,
+                                   job->run0_steps ? &info : NULL);
+                if (job->run0_steps) {
+                    job->run0_steps[i] = info.steps;
+                    job->run0_event[i] = (int8_t)info.event;
+                    job->run0_choice[i] = (int8_t)info.choice;
+                }
             }
             if (rc != JREF_OK)
                 __atomic_store_n(&job->error, rc, __ATOMIC_RELAXED);
@@ -579,7 +601,8 @@ int jref_classify(const uint64_t* genomes, int64_t n, int t, int c, int grid,
 {
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
-    job_t job = { MODE_LIST, genomes, NULL, 0, n, t, c, grid, runs, seed, out, 0, 0 };
+    job_t job = { MODE_LIST, genomes, NULL, 0, n, t, c, grid, runs, seed, out,
+                  NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -588,7 +611,21 @@ int jref_classify_range(uint64_t first, int64_t n, int t, int c, int grid,
 {
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
-    job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out, 0, 0 };
+    job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
+                  NULL, NULL, NULL, 0, 0 };
+    return run_job(&job, threads);
+}
+
+int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
+                             int runs, uint64_t seed, jref_result_t* out,
+                             int32_t* run0_steps, int8_t* run0_event,
+                             int8_t* run0_choice, int threads)
+{
+    if (jref_check_args(t, c, grid, runs) != JREF_OK || !run0_steps || !run0_event ||
+        !run0_choice)
+        return JREF_E_INVALID_ARG;
+    job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
+                  run0_steps, run0_event, run0_choice, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -597,6 +634,7 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
 {
     if (jref_check_args(1, c, 16, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
-    job_t job = { MODE_ITEMS, NULL, items, 0, n, 1, c, 16, runs, seed, out, 0, 0 };
+    job_t job = { MODE_ITEMS, NULL, items, 0, n, 1, c, 16, runs, seed, out,
+                  NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }

@@ -98,6 +98,15 @@ int jref_classify_range(uint64_t first, int64_t n, int t, int c, int grid,
 int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
                         uint64_t seed, jref_result_t* out, int threads);
 
+/* Same as jref_classify_range, also reporting the first run of every
+ * genotype: its placements, its event (0 none, 1 unbound, 2 ambiguous) and
+ * whether it ever had two frontier sites to choose from.  Used to account
+ * the work of each stage of a pipelined implementation. */
+int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
+                             int runs, uint64_t seed, jref_result_t* out,
+                             int32_t* run0_steps, int8_t* run0_event,
+                             int8_t* run0_choice, int threads);
+
 /* Traces one run: writes the placed cells in placement order (y*(G+1)+x,
  * seed first) to cells_out (capacity cap) and returns the event code of the
  * run (0 none/done, 1 unbound, 2 ambiguous) through *event.  Returns the

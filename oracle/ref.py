@@ -60,6 +60,11 @@ def lib() -> ctypes.CDLL:
                                           ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
                                           ctypes.c_int]
         L.jref_classify_items.restype = ctypes.c_int
+        L.jref_classify_range_run0.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.jref_classify_range_run0.restype = ctypes.c_int
         L.jref_trace_run.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_int,
@@ -128,6 +133,20 @@ def classify_range(first: int, n: int, t: int, c: int = 8, grid: int = 16, runs:
     if rc != 0:
         raise ValueError(f"oracle rejected arguments (rc={rc})")
     return out
+
+
+def classify_range_run0(first: int, n: int, t: int, c: int = 8, grid: int = 16,
+                        runs: int = 20, seed: int = 1, threads: int = 0):
+    """Records plus (steps, event, choice) of every genotype's first run."""
+    out = np.zeros(n, dtype=RECORD)
+    s0 = np.zeros(n, dtype=np.int32)
+    e0 = np.zeros(n, dtype=np.int8)
+    c0 = np.zeros(n, dtype=np.int8)
+    rc = lib().jref_classify_range_run0(first, n, t, c, grid, runs, seed, out.ctypes.data,
+                                        s0.ctypes.data, e0.ctypes.data, c0.ctypes.data, threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out, s0, e0, c0
 
 
 def classify_items(items: np.ndarray, c: int = 8, runs: int = 20, seed: int = 1,

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace jatam {
 
 // ---------------------------------------------------------------------------
@@ -65,21 +67,29 @@ __device__ __forceinline__ uint32_t oaat_finish(uint32_t h)
 }
 
 // ---------------------------------------------------------------------------
-// A decoded genotype.
+// A decoded genotype of at most TM tiles (TM = 2 or 4).
 //
 // Oriented tile k = 4*i + r is tile i turned clockwise by r quarter turns; it
 // is held as a 16-bit word of four nibbles, side d (N=0, E=1, S=2, W=3) in
-// bits 4d..4d+3.  For every side s the colours that all oriented tiles show
-// on s are packed as nibble k of side_cols[s], so one SWAR comparison finds
-// every oriented tile that shows a given colour there.  `reps` has bit 4k+3
-// set for each k that is the first oriented tile with its colour tuple:
+// bits 4d..4d+3.  For every side s the colours that all 4*TM oriented tiles
+// show on s are packed as nibble k of side_cols[s], so one SWAR comparison
+// finds every oriented tile that shows a given colour there.  `reps` has bit
+// 4k+3 set for each k that is the first oriented tile with its colour tuple:
 // duplicates and symmetric orientations collapse onto that representative.
+// With TM = 2 every word is 32 bits, with TM = 4 64 bits.
 // ---------------------------------------------------------------------------
+template <int TM>
 struct Model {
-    uint32_t tile[4];        // tile i, nibble d = colour of side d
-    uint64_t side_cols[4];   // nibble k = colour oriented tile k shows on side s
-    uint64_t reps;           // bit 4k+3 set for representative oriented tiles
-    int c;                   // colour count
+    static_assert(TM == 2 || TM == 4, "TM must be 2 or 4");
+    using Word = typename std::conditional<TM == 2, uint32_t, uint64_t>::type;
+    static constexpr int kOriented = 4 * TM;
+    static constexpr Word kOnes = (Word)0x1111111111111111ull;
+    static constexpr Word kLow3 = (Word)0x7777777777777777ull;
+
+    Word tiles;          // tile i in bits 16i..16i+15, nibble d = colour of side d
+    Word side_cols[4];   // nibble k = colour oriented tile k shows on side s
+    Word reps;           // bit 4k+3 set for representative oriented tiles
+    int c;               // colour count
 };
 
 __device__ __forceinline__ uint32_t rotate_tile(uint32_t tile, int r)
@@ -89,12 +99,16 @@ __device__ __forceinline__ uint32_t rotate_tile(uint32_t tile, int r)
     return ((tile << s) | (tile >> ((16u - s) & 15u))) & 0xFFFFu;
 }
 
-__device__ __forceinline__ Model build_model(uint64_t genome, int t, int bits, int c)
+template <int TM>
+__device__ __forceinline__ Model<TM> build_model(uint64_t genome, int t, int bits, int c)
 {
-    Model m;
+    using M = Model<TM>;
+    using Word = typename M::Word;
+    M m;
     const uint32_t cmask = (uint32_t)c - 1u;
+    uint32_t tile[TM];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TM; ++i) {
         uint32_t w = 0;
         if (i < t) {
 #pragma unroll
@@ -103,65 +117,79 @@ __device__ __forceinline__ Model build_model(uint64_t genome, int t, int bits, i
                 w |= (uint32_t)((genome >> shift) & cmask) << (4 * d);
             }
         }
-        m.tile[i] = w;
+        tile[i] = w;
     }
-    m.side_cols[0] = m.side_cols[1] = m.side_cols[2] = m.side_cols[3] = 0;
-    uint32_t oriented[16];
+    m.tiles = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
+        m.tiles |= (Word)tile[i] << (16 * i);
+    m.side_cols[0] = m.side_cols[1] = m.side_cols[2] = m.side_cols[3] = 0;
+    uint32_t oriented[M::kOriented];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            oriented[4 * i + r] = rotate_tile(m.tile[i], r);
+            oriented[4 * i + r] = rotate_tile(tile[i], r);
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
+    for (int k = 0; k < M::kOriented; ++k)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            m.side_cols[s] |= (uint64_t)((oriented[k] >> (4 * s)) & 15u) << (4 * k);
-    uint64_t reps = 0;
+            m.side_cols[s] |= (Word)((oriented[k] >> (4 * s)) & 15u) << (4 * k);
+    Word reps = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < M::kOriented; ++k) {
         bool first = k < 4 * t;
 #pragma unroll
         for (int k2 = 0; k2 < k; ++k2)
             first = first && (oriented[k2] != oriented[k]);
-        reps |= first ? (uint64_t)8u << (4 * k) : 0;
+        reps |= first ? (Word)8u << (4 * k) : (Word)0;
     }
     m.reps = reps;
     m.c = c;
     return m;
 }
 
-// Colour tuple of oriented tile k (k < 16).
-__device__ __forceinline__ uint32_t oriented_tile(const Model& m, int k)
+// Colour tuple of oriented tile k: a shift, never an indexed load.
+template <int TM>
+__device__ __forceinline__ uint32_t oriented_tile(const Model<TM>& m, int k)
 {
-    const int i = k >> 2;
-    uint32_t w = m.tile[0];
-    w = i == 1 ? m.tile[1] : w;
-    w = i == 2 ? m.tile[2] : w;
-    w = i == 3 ? m.tile[3] : w;
+    const uint32_t w = (uint32_t)(m.tiles >> (16 * (k >> 2))) & 0xFFFFu;
     return rotate_tile(w, k & 3);
 }
 
-// Bonding options of the empty site next to oriented tile `a` in direction d:
-// the distinct representatives that show the partner of a's side-d colour on
-// their side facing back.  Returns min(count, 2) in bits 4..5 and the lowest
-// representative id in bits 0..3.
-__device__ __forceinline__ uint32_t site_options(const Model& m, uint32_t tuple, int d)
+// Colour tuple of the seed: tile 0, unrotated.
+template <int TM>
+__device__ __forceinline__ uint32_t seed_tile(const Model<TM>& m)
 {
+    return (uint32_t)m.tiles & 0xFFFFu;
+}
+
+// Bonding options of the empty site next to a placed tile (colour tuple
+// `tuple`) in direction d: the distinct representatives that show the
+// partner of the tile's side-d colour on their side facing back.  Returns
+// min(count, 2) in bits 4..5 and the lowest representative id in bits 0..3
+// (0 when nothing bonds).
+template <int TM>
+__device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tuple, int d)
+{
+    using M = Model<TM>;
+    using Word = typename M::Word;
     const int x = (int)((tuple >> (4 * d)) & 15u);
     // partner colour: 1<->2, 3<->4, ...; 0 and a last odd colour have none
     const int p = ((x + 1) ^ 1) - 1;
     if (p < 0 || p >= m.c)
         return 0;
-    const uint64_t ones = 0x1111111111111111ull;
-    const uint64_t low3 = 0x7777777777777777ull;
-    const uint64_t v = m.side_cols[(d + 2) & 3] ^ (ones * (uint64_t)p);
+    const Word v = m.side_cols[(d + 2) & 3] ^ (M::kOnes * (Word)p);
     // high bit of each nibble set iff the nibble is nonzero (no carries escape)
-    const uint64_t nonzero = v | ((v & low3) + low3);
-    const uint64_t match = ~nonzero & m.reps;
+    const Word nonzero = v | ((v & M::kLow3) + M::kLow3);
+    const Word match = ~nonzero & m.reps;
     if (match == 0)
         return 0;
-    const uint32_t id = (uint32_t)__builtin_ctzll(match) >> 2;
+    uint32_t id;
+    if constexpr (TM == 2)
+        id = (uint32_t)__builtin_ctz((uint32_t)match) >> 2;
+    else
+        id = (uint32_t)__builtin_ctzll((uint64_t)match) >> 2;
     const uint32_t count = (match & (match - 1)) ? 2u : 1u;
     return (count << 4) | id;
 }

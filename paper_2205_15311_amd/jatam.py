@@ -49,6 +49,26 @@ def lib() -> ctypes.CDLL:
         L.jatam_strerror.restype = ctypes.c_char_p
         L.jatam_abi_version.argtypes = []
         L.jatam_abi_version.restype = i32
+        L.jatam_batch_create.argtypes = [i64, ctypes.POINTER(vp)]
+        L.jatam_batch_create.restype = i32
+        L.jatam_batch_destroy.argtypes = [vp]
+        L.jatam_batch_destroy.restype = i32
+        L.jatam_batch_classify.argtypes = [vp, vp, i64, i32, i32, i32, i32, u64, vp, vp, vp]
+        L.jatam_batch_classify.restype = i32
+        L.jatam_batch_classify_range.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64, vp, vp,
+                                                 vp]
+        L.jatam_batch_classify_range.restype = i32
+        L.jatam_batch_classify_items.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
+        L.jatam_batch_classify_items.restype = i32
+        L.jatam_batch_set_refill.argtypes = [vp, i32]
+        L.jatam_batch_set_refill.restype = i32
+        L.jatam_batch_set_timing.argtypes = [vp, i32]
+        L.jatam_batch_set_timing.restype = i32
+        L.jatam_batch_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int), i32]
+        L.jatam_batch_stage_times.restype = i32
+        L.jatam_batch_stage_name.argtypes = [i32]
+        L.jatam_batch_stage_name.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -111,3 +131,124 @@ def records_to_numpy(rec: torch.Tensor):
     import numpy as np
     dt = np.dtype([("cls", "<i4"), ("size", "<i4"), ("hash", "<u4"), ("steps", "<i4")])
     return rec.detach().cpu().contiguous().numpy().view(dt).reshape(-1)
+
+
+# jatam_item_t: uint64 genome, uint64 rng_id, uint8 t, uint8 grid, 6 pad bytes
+ITEM_BYTES = 24
+
+
+def make_items(genomes, t, grid, rng_ids=None):
+    """Packs per-item genomes, tile counts and grids (numpy arrays) into the
+    24-byte jatam_item_t layout; returns a uint8 numpy array of shape (n, 24)."""
+    import numpy as np
+    genomes = np.asarray(genomes, dtype=np.uint64)
+    n = genomes.shape[0]
+    t = np.broadcast_to(np.asarray(t, dtype=np.uint8), (n,))
+    grid = np.broadcast_to(np.asarray(grid, dtype=np.uint8), (n,))
+    if rng_ids is None:
+        rng_ids = genomes | (t.astype(np.uint64) << np.uint64(56))
+    dt = np.dtype([("genome", "<u8"), ("rng_id", "<u8"), ("t", "u1"), ("grid", "u1"),
+                   ("pad", "u1", (6,))])
+    arr = np.zeros(n, dtype=dt)
+    arr["genome"] = genomes
+    arr["rng_id"] = rng_ids
+    arr["t"] = t
+    arr["grid"] = grid
+    return arr.view(np.uint8).reshape(n, ITEM_BYTES)
+
+
+class Batch:
+    """A jatam_batch_t workspace (device queues for up to max_n genotypes per
+    call) and the pipelined calls that use it."""
+
+    def __init__(self, max_n: int):
+        handle = ctypes.c_void_p()
+        _check(lib().jatam_batch_create(int(max_n), ctypes.byref(handle)), "jatam_batch_create")
+        self._h = handle
+        self.max_n = int(max_n)
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().jatam_batch_destroy(self._h), "jatam_batch_destroy")
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _tally_ptr(tally):
+        if tally is None:
+            return None
+        if tally.dtype != torch.int64 or tuple(tally.shape) != (4,) or not tally.is_cuda:
+            raise ValueError("tally must be a device int64 tensor of shape (4,)")
+        return tally.data_ptr()
+
+    def classify(self, genotypes: torch.Tensor, t: int, c: int = 8, grid_limit: int = 16,
+                 runs: int = 20, seed: int = 1, out: torch.Tensor | None = None,
+                 tally: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """jatam_batch_classify."""
+        if genotypes.dtype not in (torch.int64, torch.uint64) or genotypes.dim() != 1:
+            raise ValueError("genotypes must be a 1-D int64/uint64 tensor")
+        if not genotypes.is_cuda or not genotypes.is_contiguous():
+            raise ValueError("genotypes must be a contiguous device tensor")
+        n = genotypes.shape[0]
+        rec = _records(n, genotypes.device, out)
+        rc = lib().jatam_batch_classify(self._h, genotypes.data_ptr(), n, t, c, grid_limit,
+                                        runs, seed, rec.data_ptr(), self._tally_ptr(tally),
+                                        _stream_handle(stream))
+        _check(rc, "jatam_batch_classify")
+        return rec
+
+    def classify_range(self, first: int, n: int, t: int, c: int = 8, grid_limit: int = 16,
+                       runs: int = 20, seed: int = 1, out: torch.Tensor | None = None,
+                       tally: torch.Tensor | None = None, device="cuda",
+                       stream=None) -> torch.Tensor:
+        """jatam_batch_classify_range."""
+        rec = _records(n, device, out)
+        rc = lib().jatam_batch_classify_range(self._h, first, n, t, c, grid_limit, runs, seed,
+                                              rec.data_ptr(), self._tally_ptr(tally),
+                                              _stream_handle(stream))
+        _check(rc, "jatam_batch_classify_range")
+        return rec
+
+    def classify_items(self, items: torch.Tensor, c: int = 8, runs: int = 20, seed: int = 1,
+                       out: torch.Tensor | None = None, tally: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+        """jatam_batch_classify_items; items is a device uint8 tensor (n, 24)."""
+        if items.dtype != torch.uint8 or items.dim() != 2 or items.shape[1] != ITEM_BYTES:
+            raise ValueError("items must be a uint8 tensor of shape (n, 24)")
+        if not items.is_cuda or not items.is_contiguous():
+            raise ValueError("items must be a contiguous device tensor")
+        n = items.shape[0]
+        rec = _records(n, items.device, out)
+        rc = lib().jatam_batch_classify_items(self._h, items.data_ptr(), n, c, runs, seed,
+                                              rec.data_ptr(), self._tally_ptr(tally),
+                                              _stream_handle(stream))
+        _check(rc, "jatam_batch_classify_items")
+        return rec
+
+    def set_refill(self, idle_lanes: int) -> None:
+        _check(lib().jatam_batch_set_refill(self._h, idle_lanes), "jatam_batch_set_refill")
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().jatam_batch_set_timing(self._h, 1 if enable else 0),
+               "jatam_batch_set_timing")
+
+    def stage_times(self) -> dict:
+        """{stage name: (summed ms, calls)} over the calls made while timing."""
+        ms = (ctypes.c_double * 8)()
+        calls = (ctypes.c_int * 8)()
+        k = lib().jatam_batch_stage_times(self._h, ms, calls, 8)
+        if k < 0:
+            raise JatamError(k, "jatam_batch_stage_times")
+        return {lib().jatam_batch_stage_name(s).decode(): (ms[s], calls[s]) for s in range(k)
+                if calls[s] > 0}

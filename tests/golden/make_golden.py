@@ -22,12 +22,30 @@ from oracle import ref  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def slice_summary(recs):
+def slice_summary(recs, s0, e0, c0, runs):
+    det = recs["cls"] == 3
+    size = recs["size"].astype(np.int64)
+    steps = recs["steps"].astype(np.int64)
+    # how the work splits over a pipeline: genotypes the seed alone decides
+    # (0 placements), first runs, and the repeat runs of candidates whose
+    # first run drew a random word and ended without an event
+    cand = (e0 == 0) & (c0 == 1) & (runs > 1)
+    first_only = ~cand
     return {
         "sha256": hashlib.sha256(recs.tobytes()).hexdigest(),
         "tally": [int(np.sum(recs["cls"] == k)) for k in range(4)],
-        "steps": int(recs["steps"].astype(np.int64).sum()),
-        "det_size": int(recs["size"][recs["cls"] == 3].astype(np.int64).sum()),
+        "steps": int(steps.sum()),
+        "det_size": int(size[det].sum()),
+        "work": {
+            "run0_steps": int(s0.astype(np.int64).sum()),
+            "monomer_det": int(np.sum(det & (size == 1))),
+            "run0_det": int(np.sum(det & first_only & (size > 1))),
+            "run0_det_size": int(size[det & first_only & (size > 1)].sum()),
+            "candidates": int(cand.sum()),
+            "repeat_steps": int((steps[cand] - s0[cand]).sum()),
+            "repeat_det": int(np.sum(det & cand)),
+            "repeat_det_size": int(size[det & cand].sum()),
+        },
     }
 
 
@@ -36,8 +54,8 @@ def make(t, grid, runs, seed, total, slice_n, path):
     slices = []
     for first in range(0, total, slice_n):
         n = min(slice_n, total - first)
-        recs = ref.classify_range(first, n, t, grid=grid, runs=runs, seed=seed)
-        s = slice_summary(recs)
+        recs, s0, e0, c0 = ref.classify_range_run0(first, n, t, grid=grid, runs=runs, seed=seed)
+        s = slice_summary(recs, s0, e0, c0, runs)
         s["first"] = first
         s["n"] = n
         slices.append(s)
@@ -49,6 +67,7 @@ def make(t, grid, runs, seed, total, slice_n, path):
         "tally": [sum(s["tally"][k] for s in slices) for k in range(4)],
         "steps": sum(s["steps"] for s in slices),
         "det_size": sum(s["det_size"] for s in slices),
+        "work": {k: sum(s["work"][k] for s in slices) for k in slices[0]["work"]},
     }
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)
