@@ -48,15 +48,17 @@ struct LaneGrid {
 
     __device__ __forceinline__ bool occupied(int p) { return (occ(p >> 5) >> (p & 31)) & 1u; }
     __device__ __forceinline__ bool on_frontier(int p) { return (fr(p >> 5) >> (p & 31)) & 1u; }
-    __device__ __forceinline__ uint32_t pend(int p)
+    // every word of the lane's grid, PEND included (kernel start)
+    __device__ __forceinline__ void clear_all()
     {
-        return (word(Geo::kPend + (p >> 3)) >> ((p & 7) * 4)) & 15u;
+        for (int k = 0; k < Geo::kLaneWords; ++k)
+            word(k) = 0;
     }
-    __device__ __forceinline__ void set_pend(int p, uint32_t id)
+    __device__ __forceinline__ uint32_t& pend_word(int p) { return word(Geo::kPend + (p >> 3)); }
+    // LDS atomic OR without return: sets bits with no read on the critical path
+    __device__ __forceinline__ static void set_bits(uint32_t& w, uint32_t bits)
     {
-        uint32_t& w = word(Geo::kPend + (p >> 3));
-        const int sh = (p & 7) * 4;
-        w = (w & ~(15u << sh)) | (id << sh);
+        __hip_atomic_fetch_or(&w, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __device__ __forceinline__ uint32_t row(int y)
     {
@@ -98,35 +100,52 @@ struct RunState {
 };
 
 // The tile `tuple` was just placed at p: check its empty neighbours (§3.2).
+// A bondable site on the ring means the structure leaves the box; a site
+// that two distinct tiles can fill is ambiguous; otherwise a free site with
+// one admissible tile joins the frontier with that tile pending.  All reads
+// of the four neighbours are issued before any of them is used.
+//
+// Invariant: the PEND nibble of a cell is zero unless the cell is on the
+// frontier, so a new pending tile is written with one LDS atomic OR.
 template <int W, int B, int TM>
 __device__ __forceinline__ int update_site(const Model<TM>& m, LaneGrid<W, B>& g, RunState& st,
                                            int G, int p, uint32_t tuple)
 {
     constexpr int kMask = W * W - 1;
+    uint32_t opt[4], ow[4], fw[4], pw[4];
+    int q[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
+        q[d] = (p + delta) & kMask;
+        opt[d] = site_options(m, tuple, d);
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        ow[d] = g.occ(q[d] >> 5);
+        fw[d] = g.fr(q[d] >> 5);
+        pw[d] = g.pend_word(q[d]);
+    }
     bool unbound = false, ambiguous = false;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const uint32_t opt = site_options(m, tuple, d);
-        if (opt == 0)
-            continue;
-        const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
-        const int q = (p + delta) & kMask;
-        const int qx = q & (W - 1), qy = q >> Geometry<W>::kLogW;
-        if (qx >= G - 1 || qy >= G - 1) {
-            unbound = true;              // bondable site outside the box
-            continue;
-        }
-        if (g.occupied(q))
-            continue;
-        const uint32_t id = opt & 15u;
-        if ((opt >> 4) >= 2) {
-            ambiguous = true;            // two distinct tiles bond here
-        } else if (g.on_frontier(q)) {
-            ambiguous = ambiguous || g.pend(q) != id;
-        } else {
-            g.fr(q >> 5) |= 1u << (q & 31);
-            g.set_pend(q, id);
-            st.fsum |= 1u << (q >> 5);
+        const int qx = q[d] & (W - 1), qy = q[d] >> Geometry<W>::kLogW;
+        const bool ring = qx >= G - 1 || qy >= G - 1;
+        const uint32_t bit = (uint32_t)q[d] & 31u;
+        const bool has = opt[d] != 0;
+        const bool free = ((ow[d] >> bit) & 1u) == 0;
+        const bool live = has && !ring && free;
+        const uint32_t id = opt[d] & 15u;
+        const bool multi = (opt[d] >> 4) >= 2;
+        const bool in_f = ((fw[d] >> bit) & 1u) != 0;
+        const uint32_t sh = ((uint32_t)q[d] & 7u) * 4u;
+        const uint32_t pending = (pw[d] >> sh) & 15u;
+        unbound = unbound || (has && ring);
+        ambiguous = ambiguous || (live && (multi || (in_f && pending != id)));
+        if (live && !multi && !in_f) {
+            LaneGrid<W, B>::set_bits(g.fr(q[d] >> 5), 1u << bit);
+            LaneGrid<W, B>::set_bits(g.pend_word(q[d]), id << sh);
+            st.fsum |= 1u << (q[d] >> 5);
             st.nf += 1;
         }
     }
@@ -147,8 +166,15 @@ __device__ __forceinline__ int run_start(const Model<TM>& m, LaneGrid<W, B>& g, 
 {
     for (uint32_t s = st.osum; s; s &= s - 1)
         g.occ(__builtin_ctz(s)) = 0;
-    for (uint32_t s = st.fsum; s; s &= s - 1)
-        g.fr(__builtin_ctz(s)) = 0;
+    // a run that ended on an event leaves frontier cells (and their PEND
+    // nibbles) behind: clear both
+    for (uint32_t s = st.fsum; s; s &= s - 1) {
+        const int w = __builtin_ctz(s);
+        g.fr(w) = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            g.word(Geometry<W>::kPend + 4 * w + k) = 0;
+    }
     st.nf = 0;
     st.fsum = 0;
     st.size = 1;
@@ -192,20 +218,41 @@ __device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, R
         j = __umulhi(u, st.nf);
     }
     // the j-th frontier site in row-major order
-    uint32_t fs = st.fsum;
     int w = 0;
     uint32_t fw = 0;
-    while (fs != 0) {
-        w = __builtin_ctz(fs);
-        fw = g.fr(w);
-        const uint32_t c = __popc(fw);
-        if (j < c)
-            break;
-        j -= c;
-        fs &= fs - 1;
+    if constexpr (W == 16) {
+        // 8 frontier words: load all, pick the word by prefix counts, no loop
+        uint32_t f[Geometry<W>::kWords];
+#pragma unroll
+        for (int k = 0; k < Geometry<W>::kWords; ++k)
+            f[k] = g.fr(k);
+        uint32_t acc = 0, rank = 0;
+#pragma unroll
+        for (int k = 0; k < Geometry<W>::kWords; ++k) {
+            const uint32_t c = __popc(f[k]);
+            const bool hit = j >= acc && j < acc + c;
+            fw = hit ? f[k] : fw;
+            w = hit ? k : w;
+            rank = hit ? j - acc : rank;
+            acc += c;
+        }
+        if (acc != st.nf)
+            return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
+        j = rank;
+    } else {
+        uint32_t fs = st.fsum;
+        while (fs != 0) {
+            w = __builtin_ctz(fs);
+            fw = g.fr(w);
+            const uint32_t c = __popc(fw);
+            if (j < c)
+                break;
+            j -= c;
+            fs &= fs - 1;
+        }
+        if (fs == 0)
+            return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
     }
-    if (fs == 0)
-        return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
     const int bit = select_bit(fw, j);
     const int p = (w << 5) | bit;
     fw &= ~(1u << bit);
@@ -214,8 +261,13 @@ __device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, R
         st.fsum &= ~(1u << w);
     st.nf -= 1;
 
-    const uint32_t tuple = oriented_tile(m, (int)g.pend(p));
-    g.occ(w) |= 1u << bit;
+    // take the pending tile and clear its nibble (it leaves the frontier)
+    uint32_t& pwr = g.pend_word(p);
+    const uint32_t pw = pwr;
+    const uint32_t sh = ((uint32_t)p & 7u) * 4u;
+    pwr = pw & ~(15u << sh);
+    const uint32_t tuple = oriented_tile(m, (int)((pw >> sh) & 15u));
+    LaneGrid<W, B>::set_bits(g.occ(w), 1u << bit);
     st.osum |= 1u << w;
     st.size += 1;
     st.steps += 1;
@@ -304,15 +356,111 @@ __device__ __forceinline__ uint32_t combine_orientations(uint32_t hs[8])
     return oaat_finish(hv);
 }
 
+// ---------------------------------------------------------------------------
+// Register-only D4 hash for shapes whose bounding box fits 8 x 8: the cropped
+// shape is a 64-bit bitmap, bit 8*y + x, so row-major cell order is ascending
+// bit order.  The 8 images are the 4 mirror combinations of the shape and of
+// its transpose, each re-anchored at (0, 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t bytes_reversed(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    return ((uint64_t)__builtin_bswap32(lo) << 32) | __builtin_bswap32(hi);
+}
+
+// Mirror x: reverse the bits of every byte, then shift the shape back to x=0.
+__device__ __forceinline__ uint64_t mirror_x8(uint64_t v, int w)
+{
+    const uint32_t lo = __builtin_bitreverse32((uint32_t)v);
+    const uint32_t hi = __builtin_bitreverse32((uint32_t)(v >> 32));
+    // bit-reversing each half also reversed byte order: undo that
+    const uint64_t r = ((uint64_t)__builtin_bswap32(hi) << 32) | __builtin_bswap32(lo);
+    return r >> (8 - w);
+}
+
+// Mirror y: reverse the row order, then shift the shape back to y=0.
+__device__ __forceinline__ uint64_t mirror_y8(uint64_t v, int h)
+{
+    return bytes_reversed(v) >> (8 * (8 - h));
+}
+
+// Transpose of an 8 x 8 bit matrix (bit 8*y + x -> bit 8*x + y).
+__device__ __forceinline__ uint64_t transpose8(uint64_t x)
+{
+    uint64_t t;
+    t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x = x ^ t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x = x ^ t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x = x ^ t ^ (t << 28);
+    return x;
+}
+
+// OAAT over (x, y) of every set cell in ascending bit (row-major) order.
+__device__ __forceinline__ uint32_t bitmap_hash8(uint64_t v)
+{
+    uint32_t h = 0;
+    while (v != 0) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(v);
+        v &= v - 1;
+        h = oaat_add(h, b & 7u);
+        h = oaat_add(h, b >> 3);
+    }
+    return oaat_finish(h);
+}
+
+// Image k (0..7) of the w x h shape m: bit 2 transposes, bit 0 mirrors x,
+// bit 1 mirrors y (in the transposed frame when transposed).
+__device__ __forceinline__ uint64_t image8(uint64_t m, int w, int h, int k)
+{
+    uint64_t v = m;
+    int ww = w, hh = h;
+    if (k & 4) {
+        v = transpose8(v);
+        ww = h;
+        hh = w;
+    }
+    if (k & 1)
+        v = mirror_x8(v, ww);
+    if (k & 2)
+        v = mirror_y8(v, hh);
+    return v;
+}
+
+// The cropped shape held in OCC as an 8 x 8 bitmap; false if it does not fit.
+template <int W, int B>
+__device__ __forceinline__ bool shape_bitmap8(LaneGrid<W, B>& g, int G, uint64_t& m, int& w,
+                                              int& h)
+{
+    const ShapeBox bx = crop(g, G);
+    w = bx.w;
+    h = bx.h;
+    if (bx.w > 8 || bx.h > 8)
+        return false;
+    m = 0;
+    for (int y = 0; y < bx.h; ++y)
+        m |= (uint64_t)((g.row(bx.ymin + y) >> bx.xmin) & 0xFFu) << (8 * y);
+    return true;
+}
+
 // D4-invariant hash of the shape held in OCC, computed by one lane.
 template <int W, int B>
 __device__ uint32_t shape_hash(LaneGrid<W, B>& g, int G)
 {
-    const ShapeBox bx = crop(g, G);
     uint32_t hs[8];
+    uint64_t m;
+    int w, h;
+    if (shape_bitmap8(g, G, m, w, h)) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        hs[k] = orientation_hash(g, bx, k);
+        for (int k = 0; k < 8; ++k)
+            hs[k] = bitmap_hash8(image8(m, w, h, k));
+    } else {
+        const ShapeBox bx = crop(g, G);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            hs[k] = orientation_hash(g, bx, k);
+    }
     return combine_orientations(hs);
 }
 

@@ -117,8 +117,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t ring[kRing];
     LaneGrid<W, 64> g{smem + threadIdx.x};
-    for (int w = 0; w < 2 * Geo::kWords; ++w)
-        g.word(w) = 0;
+    g.clear_all();
     RunState st{0, 0, 0, 0, 0, false};
     DrawCache dc;
     dc.block = 0xFFFFFFFFu;
@@ -326,17 +325,24 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
 // ---------------------------------------------------------------------------
 // repeat<W>: all R runs of a candidate at once, one lane per run.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_inclusive_sum(int v)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        v += lane_id() >= off ? u : 0;
+    }
+    return v;
+}
+
 template <int W, int TM>
 __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
-    __shared__ uint32_t res[4][64];      // ev, size, steps, same-as-run-0 per lane
-    __shared__ uint32_t verdict[64];     // per group: class | witness run << 8
     __shared__ uint32_t orient[8][64];   // per group: the 8 orientation hashes
     LaneGrid<W, 64> g{smem + threadIdx.x};
-    for (int w = 0; w < 2 * Geo::kWords; ++w)
-        g.word(w) = 0;
+    g.clear_all();
     RunState st{0, 0, 0, 0, 0, false};
     WaveTally tally{{0, 0, 0, 0}};
 
@@ -345,81 +351,81 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
     const int lane = (int)threadIdx.x;
     const int grp = lane / R, run = lane - grp * R;
     const int lead = grp * R;                         // lane making run 0
+    const int tail = lead + R - 1;                    // lane making run R-1
+    const uint64_t gmask = R == 64 ? ~0ull : ((1ull << R) - 1);
     LaneGrid<W, 64> g0{smem + lead};
     const uint32_t count = a.ws.counters[kCntCand + klass];
     const uint32_t* queue = a.ws.sorted[klass];
+    const uint32_t stride = gridDim.x * (uint32_t)groups;
 
-    // static round-robin over the size-sorted queue
-    for (uint32_t base = blockIdx.x * (uint32_t)groups; base < count;
-         base += gridDim.x * (uint32_t)groups) {
+    // static round-robin over the size-sorted queue; the next entry is
+    // fetched one iteration ahead
+    uint32_t base = blockIdx.x * (uint32_t)groups;
+    uint32_t next_idx = 0;
+    if (grp < groups && base + (uint32_t)grp < count)
+        next_idx = queue[base + grp];
+    for (; base < count; base += stride) {
         const bool active = grp < groups && base + (uint32_t)grp < count;
-        uint32_t idx = 0;
+        const uint32_t idx = next_idx;
+        if (grp < groups && base + stride + (uint32_t)grp < count)
+            next_idx = queue[base + stride + grp];
         Geno gd{0, 0, 0, 0, false};
         int ev = kEvNone;
         if (active) {
-            idx = queue[base + grp];
             gd = fetch_geno(a, idx);
             const Model<TM> m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
             ev = run_assembly(m, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
                               (uint32_t)(gd.rng_id >> 32));
         }
-        __syncthreads();
-        if (active) {
-            bool same = true;
-            if (run > 0 && ev == kEvNone) {
+        __syncthreads();   // every run's grid is final
+        // a witness is a later run that hit an event or ended in another shape
+        bool same = true;
+        if (active && run > 0 && ev == kEvNone) {
 #pragma unroll
-                for (int w = 0; w < Geo::kWords; ++w)
-                    same = same && g.occ(w) == g0.occ(w);
-            }
-            res[0][lane] = (uint32_t)ev;
-            res[1][lane] = (uint32_t)st.size;
-            res[2][lane] = (uint32_t)st.steps;
-            res[3][lane] = same ? 1u : 0u;
+            for (int w = 0; w < Geo::kWords; ++w)
+                same = same && g.occ(w) == g0.occ(w);
         }
-        __syncthreads();
-        if (active && run == 0) {
-            // first witness in run order (§3.2)
-            int cls = JATAM_DET, witness = 0;
-            for (int r = 1; r < R; ++r) {
-                const uint32_t e = res[0][lead + r];
-                if (e != kEvNone) {
-                    cls = e == kEvUnbound ? JATAM_UNBOUND
-                        : e == kEvAmbig   ? JATAM_ND_SITE
-                                          : JATAM_INVALID;
-                    witness = r;
-                    break;
-                }
-                if (res[3][lead + r] == 0) {
-                    cls = JATAM_ND_RUNS;
-                    witness = r;
-                    break;
-                }
-            }
-            if (ev == kEvCorrupt)
-                cls = JATAM_INVALID;
-            verdict[grp] = (uint32_t)(cls & 0xFF) | ((uint32_t)witness << 8);
-        }
-        __syncthreads();
-        const uint32_t v = active ? verdict[grp] : 0u;
-        const int cls = (int)(int8_t)(v & 0xFF);
+        const bool witness = active && run > 0 && (ev != kEvNone || !same);
+        const uint64_t wm = (__ballot(witness) >> lead) & gmask;
+        const int first = wm ? (int)__builtin_ctzll(wm) : R;      // R: no witness
+        const int wl = lead + (first < R ? first : 0);
+        const int w_ev = __shfl(ev, wl);
+        const int w_size = __shfl(st.size, wl);
+        const int lead_ev = __shfl(ev, lead);
+        int cls;
+        if (lead_ev == kEvCorrupt || (first < R && w_ev == kEvCorrupt))
+            cls = JATAM_INVALID;
+        else if (first == R)
+            cls = JATAM_DET;
+        else
+            cls = w_ev == kEvUnbound ? JATAM_UNBOUND
+                : w_ev == kEvAmbig   ? JATAM_ND_SITE
+                                     : JATAM_ND_RUNS;
+        // placements summed over runs 0..first (all R runs if DET)
+        const int last = first < R ? first : R - 1;
+        const int incl = wave_inclusive_sum(active && run <= last ? st.steps : 0);
+        const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead);
         const bool det = active && cls == JATAM_DET;
+        const int size0 = __shfl(st.size, lead);
         // the group's lanes share the 8 orientation hashes of run 0's shape
-        if (det && res[1][lead] > 2) {
-            const ShapeBox bx = crop(g0, gd.grid);
-            for (int k = run; k < 8; k += R)
-                orient[k][grp] = orientation_hash(g0, bx, k);
+        if (det && size0 > 2) {
+            uint64_t m8;
+            int w8, h8;
+            const bool small = shape_bitmap8(g0, gd.grid, m8, w8, h8);
+            for (int k = run; k < 8; k += R) {
+                if (small) {
+                    orient[k][grp] = bitmap_hash8(image8(m8, w8, h8, k));
+                } else {
+                    const ShapeBox bx = crop(g0, gd.grid);
+                    orient[k][grp] = orientation_hash(g0, bx, k);
+                }
+            }
         }
         __syncthreads();
-        bool done = false;
-        if (active && run == 0) {
-            const int witness = (int)(v >> 8);
-            int steps = 0;
-            const int last = det ? R - 1 : witness;
-            for (int r = 0; r <= last; ++r)
-                steps += (int)res[2][lead + r];
+        const bool done = active && run == 0;
+        if (done) {
             jatam_result_t rec;
             if (det) {
-                const int size0 = (int)res[1][lead];
                 uint32_t h;
                 if (size0 <= 2) {
                     h = a.ws.small_hash[size0 - 1];
@@ -434,13 +440,12 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             } else if (cls == JATAM_INVALID) {
                 rec = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
             } else {
-                rec = jatam_result_t{cls, (int)res[1][lead + witness], 0u, steps};
+                rec = jatam_result_t{cls, w_size, 0u, steps};
             }
             a.out[idx] = rec;
-            done = true;
         }
         tally.add(done, cls);
-        __syncthreads();
+        __syncthreads();   // orientation slots and grids reused next round
     }
     tally.flush(a.tally);
 }

@@ -99,6 +99,12 @@ __device__ __forceinline__ uint32_t rotate_tile(uint32_t tile, int r)
     return ((tile << s) | (tile >> ((16u - s) & 15u))) & 0xFFFFu;
 }
 
+// Nibbles of a 16-bit tile word in reverse order (side 3 first).
+__device__ __forceinline__ uint32_t reverse_nibbles16(uint32_t t)
+{
+    return ((t & 0xFu) << 12) | ((t & 0xF0u) << 4) | ((t >> 4) & 0xF0u) | ((t >> 12) & 0xFu);
+}
+
 template <int TM>
 __device__ __forceinline__ Model<TM> build_model(uint64_t genome, int t, int bits, int c)
 {
@@ -123,26 +129,38 @@ __device__ __forceinline__ Model<TM> build_model(uint64_t genome, int t, int bit
 #pragma unroll
     for (int i = 0; i < TM; ++i)
         m.tiles |= (Word)tile[i] << (16 * i);
-    m.side_cols[0] = m.side_cols[1] = m.side_cols[2] = m.side_cols[3] = 0;
-    uint32_t oriented[M::kOriented];
+    // side s of rotation r shows colour (s - r) mod 4: over r = 0..3 that is
+    // the tile's nibbles reversed, rotated by s + 1
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int s = 0; s < 4; ++s) {
+        Word col = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            oriented[4 * i + r] = rotate_tile(tile[i], r);
-#pragma unroll
-    for (int k = 0; k < M::kOriented; ++k)
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-            m.side_cols[s] |= (Word)((oriented[k] >> (4 * s)) & 15u) << (4 * k);
+        for (int i = 0; i < TM; ++i)
+            col |= (Word)rotate_tile(reverse_nibbles16(tile[i]), (s + 1) & 3) << (16 * i);
+        m.side_cols[s] = col;
+    }
+    // representatives: the first orientation of each distinct colour tuple.
+    // Rotation r of a tile repeats rotation 0 iff the tile has r-fold symmetry;
+    // a later tile in the orbit of an earlier one repeats all of its tuples.
     Word reps = 0;
 #pragma unroll
-    for (int k = 0; k < M::kOriented; ++k) {
-        bool first = k < 4 * t;
+    for (int i = 0; i < TM; ++i) {
+        const uint32_t r1 = rotate_tile(tile[i], 1), r2 = rotate_tile(tile[i], 2);
+        const bool sym4 = r1 == tile[i];
+        const bool sym2 = r2 == tile[i];
+        uint32_t own = sym4 ? 0x1u : sym2 ? 0x3u : 0xFu;     // rotations kept
+        bool repeated = i >= t;
 #pragma unroll
-        for (int k2 = 0; k2 < k; ++k2)
-            first = first && (oriented[k2] != oriented[k]);
-        reps |= first ? (Word)8u << (4 * k) : (Word)0;
+        for (int i2 = 0; i2 < i; ++i2) {
+            const uint32_t u = tile[i2];
+            repeated = repeated || (i2 < t && (tile[i] == u || r1 == u || r2 == u ||
+                                               rotate_tile(tile[i], 3) == u));
+        }
+        own = repeated ? 0u : own;
+        // bit 4k+3 for k = 4i + r, r in own
+        const uint32_t bitsr = ((own & 1u) << 3) | ((own & 2u) << 6) | ((own & 4u) << 9) |
+                               ((own & 8u) << 12);
+        reps |= (Word)bitsr << (16 * i);
     }
     m.reps = reps;
     m.c = c;

@@ -58,8 +58,7 @@ __global__ __launch_bounds__(B) void classify_plain_kernel(const uint64_t* __res
     if (i >= n)
         return;
     LaneGrid<W, B> g{smem + threadIdx.x};
-    for (int w = 0; w < 2 * Geo::kWords; ++w)
-        g.word(w) = 0;
+    g.clear_all();
     RunState st{0, 0, 0, 0, 0, false};
 
     const uint64_t genome = genomes ? genomes[i] : first + (uint64_t)i;

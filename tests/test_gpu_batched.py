@@ -165,3 +165,18 @@ def test_refill_threshold_does_not_change_records(jt, batch):
             assert_same(got, want, f"refill={refill}")
     finally:
         batch.set_refill(24)
+
+
+@pytest.mark.parametrize("grid", [16, 32])
+def test_rare_paths_three_tiles(jt, batch, grid):
+    """400k random three-tile genotypes: enough to contain ND_RUNS genotypes
+    and DET shapes of 20-33 cells (bounding boxes beyond 8 x 8), through both
+    paths."""
+    rng = np.random.default_rng(123 + grid)
+    gs = rng.integers(0, 1 << 36, size=400_000, dtype=np.uint64)
+    want = ref.classify(gs, 3, grid=grid, runs=20, seed=1)
+    assert np.sum(want["cls"] == ref.ND_RUNS) > 10
+    assert np.sum((want["cls"] == ref.DET) & (want["size"] >= 20)) > 10
+    dev = torch.from_numpy(gs.view(np.int64)).cuda()
+    assert_same(records(batch.classify(dev, 3, 8, grid, 20, 1)), want, f"batched G={grid}")
+    assert_same(records(jt.classify(dev, 3, 8, grid, 20, 1)), want, f"plain G={grid}")
