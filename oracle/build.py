@@ -8,13 +8,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "jatam_oracle.c")
+SRCS = [os.path.join(HERE, "jatam_oracle.c"), os.path.join(HERE, "jatam_ga_oracle.c")]
 LIB = os.path.join(HERE, "libjatam_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
-           "-Wall", "-Wextra", "-Werror", "-o", LIB + ".tmp", SRC]
+           "-Wall", "-Wextra", "-Werror", "-o", LIB + ".tmp"] + SRCS
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

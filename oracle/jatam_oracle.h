@@ -115,6 +115,25 @@ int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
                    int run, uint64_t seed, int32_t* cells_out, int cap,
                    int* event, int* choice);
 
+/* ---- genetic algorithm (jatam_ga_oracle.c) ---- */
+typedef struct {
+    uint64_t seed;        /* Philox key of the GA's draws                   */
+    int tournament;       /* tournament size T, 1..8                         */
+    int mut_num, mut_den; /* per-edge mutation probability mut_num/mut_den   */
+} jref_ga_params_t;
+
+int jref_ga_check_params(const jref_ga_params_t* p, int t, int c);
+
+/* n_out offspring of generation `generation` from a population of n. */
+int jref_ga_offspring(const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c,
+                      const jref_ga_params_t* p, int32_t generation, int64_t n_out,
+                      uint64_t* out);
+
+/* One generation: n offspring and their fitness (DET size, else 0). */
+int jref_ga_step(const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c, int grid,
+                 int runs, uint64_t seed, const jref_ga_params_t* p, int32_t generation,
+                 uint64_t* next_pop, int32_t* next_fit, int threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,15 @@ def lib() -> ctypes.CDLL:
                                                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         L.jref_classify_range_run0.restype = ctypes.c_int
+        L.jref_ga_offspring.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]
+        L.jref_ga_offspring.restype = ctypes.c_int
+        L.jref_ga_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_int]
+        L.jref_ga_step.restype = ctypes.c_int
         L.jref_trace_run.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_int,
@@ -173,3 +182,38 @@ def trace_run(genome: int, t: int, run: int, c: int = 8, grid: int = 16, seed: i
         raise ValueError("oracle rejected arguments")
     W = grid + 1
     return [(int(p) % W, int(p) // W) for p in cells[:n]], int(ev.value), int(ch.value)
+
+
+class GAParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("tournament", ctypes.c_int),
+                ("mut_num", ctypes.c_int), ("mut_den", ctypes.c_int)]
+
+
+def ga_offspring(pop: np.ndarray, fit: np.ndarray, t: int, generation: int, n_out: int | None = None,
+                 c: int = 8, seed: int = 5, tournament: int = 4, mut=(1, 12)) -> np.ndarray:
+    pop = np.ascontiguousarray(pop, dtype=np.uint64)
+    fit = np.ascontiguousarray(fit, dtype=np.int32)
+    n_out = pop.shape[0] if n_out is None else n_out
+    out = np.zeros(n_out, dtype=np.uint64)
+    p = GAParams(seed, tournament, mut[0], mut[1])
+    rc = lib().jref_ga_offspring(pop.ctypes.data, fit.ctypes.data, pop.shape[0], t, c,
+                                 ctypes.byref(p), generation, n_out, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def ga_step(pop: np.ndarray, fit: np.ndarray, t: int, generation: int, c: int = 8,
+            grid: int = 32, runs: int = 20, seed: int = 1, ga_seed: int = 5,
+            tournament: int = 4, mut=(1, 12), threads: int = 0):
+    pop = np.ascontiguousarray(pop, dtype=np.uint64)
+    fit = np.ascontiguousarray(fit, dtype=np.int32)
+    nxt = np.zeros_like(pop)
+    nfit = np.zeros_like(fit)
+    p = GAParams(ga_seed, tournament, mut[0], mut[1])
+    rc = lib().jref_ga_step(pop.ctypes.data, fit.ctypes.data, pop.shape[0], t, c, grid, runs,
+                            seed, ctypes.byref(p), generation, nxt.ctypes.data, nfit.ctypes.data,
+                            threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return nxt, nfit
