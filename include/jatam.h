@@ -181,6 +181,126 @@ int jatam_batch_set_timing(jatam_batch_t* batch, int enable);
 int jatam_batch_stage_times(jatam_batch_t* batch, double* ms, int* calls, int max_stages);
 const char* jatam_batch_stage_name(int stage);
 
+/* ------------------------------------------------------------------------
+ * Genetic algorithm with assembly as fitness (§2.2, §3.1): one offspring per
+ * lane, one launch per generation (the kernel boundary is the global
+ * synchronisation the paper requires).
+ *
+ * Operators: tournament selection of `tournament` genomes drawn uniformly
+ * with replacement (fittest wins, ties to the earliest draw); uniform
+ * crossover per edge colour; per-edge mutation with probability
+ * mut_num/mut_den to a colour drawn uniformly from the other c-1; no
+ * elitism.  Offspring i of generation g draws Philox4x32-10 keyed by `seed`
+ * at counter (i, g, block, 1 << 28), word q = word q%4 of block q/4: words
+ * 0..T-1 parent A's tournament, T..2T-1 parent B's, 2T the crossover mask
+ * (bit e: edge e from B), 2T+1+e edge e's mutation test (mutate iff
+ * floor(w*den/2^32) < num), 2T+1+E+e its new colour r = floor(w*(c-1)/2^32),
+ * taken as r if r < old else r+1 (E = 4t).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;        /* Philox key of the GA's draws                   */
+    int32_t  tournament;  /* T, 1..8                                         */
+    int32_t  mut_num;     /* per-edge mutation probability mut_num/mut_den  */
+    int32_t  mut_den;
+    int32_t  pad;
+} jatam_ga_params_t;
+
+/*
+ * n_out offspring of a population of n (1 <= n < 2^32) genomes of t tiles.
+ *   pop, fit  device, n genomes and their int32 fitness
+ *   out       device, n_out genomes
+ */
+int jatam_ga_offspring(const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c,
+                       const jatam_ga_params_t* p, int32_t generation, int64_t n_out,
+                       uint64_t* out, void* stream);
+
+/*
+ * One generation: n offspring (next_pop, distinct from pop), classified by
+ * the pipelined path of `batch` (n <= its max_n; R runs on grid_limit with
+ * assembly seed `seed`), and their fitness next_fit[i] = size if DET else 0.
+ */
+int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit, int64_t n, int t,
+                  int c, int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
+                  int32_t generation, uint64_t* next_pop, int32_t* next_fit, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate MLP (not from the paper, which has no learned part).  Predicts a
+ * genotype's class and log(1 + size) from its edge colours so work can be
+ * ordered and GA offspring screened; every reported class still comes from
+ * exact assembly.
+ *
+ * x = one-hot of the 12 edge colours of up to 3 tiles (c <= 8; edge e of the
+ * genome -> input e*8 + colour; edges of absent tiles are zero), h1 =
+ * relu(x W1 + b1), h2 = relu(h1 W2 + b2), 256 wide, out = h2 W3 + b3 =
+ * (logit UNBOUND, logit ND, logit DET, log1p(size)).  Loss = mean
+ * cross-entropy (ND_SITE and ND_RUNS are one class) + mean squared error of
+ * log1p(size).  Weights are fp32 masters used as bf16, activations and hidden
+ * gradients are bf16, products accumulate in fp32 (bf16 MFMA), Adam
+ * (beta 0.9 / 0.999, eps 1e-8) updates the masters.
+ *
+ * Parameters are one fp32 vector of 91,652: w1 [96][256], b1 [256],
+ * w2 [256][256], b2 [256], w3 [256][4], b3 [4] (row-major).
+ * ------------------------------------------------------------------------ */
+typedef struct jatam_mlp jatam_mlp_t;
+
+/* Creates a network on the current device (parameters initialised He-uniform
+ * from seed 0x5eed), with activation buffers for training batches of up to
+ * max_batch (1..2^24) samples; c is the colour count (2, 4 or 8). */
+int jatam_mlp_create(int64_t max_batch, int c, jatam_mlp_t** mlp);
+int jatam_mlp_destroy(jatam_mlp_t* mlp);
+
+/* Re-initialises: w = (2u - 1) sqrt(6 / fan_in), u = Philox word / 2^32 with
+ * key `seed` at counter (index, 0, 0, 3 << 28); biases and Adam state 0. */
+int jatam_mlp_init(jatam_mlp_t* mlp, uint64_t seed, void* stream);
+
+/* Copies parameters in (device fp32 [91652]; Adam state reset) or out; grads
+ * receives the gradient of the last training step (either may be NULL). */
+int jatam_mlp_set_params(jatam_mlp_t* mlp, const float* params, void* stream);
+int jatam_mlp_get_params(jatam_mlp_t* mlp, float* params, float* grads, void* stream);
+
+/* out4[i] = network output for genome i (device, n x 4 fp32).  t: per-genome
+ * tile counts (device uint8, 1..3) or NULL for t_all. */
+int jatam_mlp_forward(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                      int64_t n, float* out4, void* stream);
+
+/* One step on a batch of n <= max_batch labelled genotypes (labels: their
+ * jatam_result_t records): forward, loss, backward, then Adam with learning
+ * rate lr (lr = 0: gradients only).  loss_out: NULL or device float[1]. */
+int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                         const jatam_result_t* labels, int64_t n, float lr, float* loss_out,
+                         void* stream);
+
+/* Screening score of each genome: P(DET) * exp(predicted log1p size) - 1,
+ * the expected size of a deterministic structure (device float [n]). */
+int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                    int64_t n, float* scores, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate-screened GA.  A generation draws oversample * n offspring
+ * (offspring i exactly as jatam_ga_offspring draws it), scores them with the
+ * surrogate, keeps the n best (score descending, ties to the lower offspring
+ * index, NaN last; kept offspring in ascending index order), and classifies
+ * only those exactly: fitness always comes from assembly.
+ * ------------------------------------------------------------------------ */
+typedef struct jatam_ga jatam_ga_t;
+
+/* Workspace for up to max_candidates offspring per generation (about 24
+ * bytes of device memory each). */
+int jatam_ga_create(int64_t max_candidates, jatam_ga_t** ga);
+int jatam_ga_destroy(jatam_ga_t* ga);
+
+/* Indices (device uint32 [k], ascending) of the k best of n scores by the
+ * rule above; n <= the workspace's max_candidates. */
+int jatam_select_top(jatam_ga_t* ga, const float* scores, int64_t n, int64_t k, uint32_t* out_idx,
+                     void* stream);
+
+/* One screened generation (t <= 3, c the network's colour count). */
+int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* mlp,
+                           const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c,
+                           int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
+                           int32_t generation, int oversample, uint64_t* next_pop,
+                           int32_t* next_fit, void* stream);
+
 /* Static description of an error code. */
 const char* jatam_strerror(int code);
 

@@ -3,6 +3,6 @@
 The work is done by the HIP library libjatam.so (include/jatam.h); this
 package only binds it.
 """
-from .jatam import (CLASS_NAMES, DET, INVALID, ND_RUNS, ND_SITE, UNBOUND, Batch,  # noqa: F401
-                    JatamError, abi_version, classify, classify_range, lib, make_items,
-                    records_to_numpy, strerror)
+from .jatam import (CLASS_NAMES, DET, GA, INVALID, MLP, ND_RUNS, ND_SITE, UNBOUND,  # noqa: F401
+                    Batch, GAParams, JatamError, abi_version, classify, classify_range, ga_offspring,
+                    lib, make_items, records_to_numpy, strerror)

@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjatam.so")
-SOURCES = ["jatam_plain.hip", "jatam_batched.hip", "jatam_api.cpp"]
+SOURCES = ["jatam_plain.hip", "jatam_batched.hip", "jatam_ga.hip", "jatam_mlp.hip",
+           "jatam_select.hip", "jatam_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -191,7 +191,8 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     const size_t staging = n + 64 * ((size_t)max_blocks + 1);
     jatam::DeviceWorkspace& ws = b->ws;
     bool ok = batch_alloc(b, jatam::kCntWords * sizeof(uint32_t), (void**)&ws.counters) &&
-              batch_alloc(b, 2 * sizeof(uint32_t), (void**)&ws.small_hash);
+              batch_alloc(b, 2 * sizeof(uint32_t), (void**)&ws.small_hash) &&
+              batch_alloc(b, n * sizeof(jatam_result_t), (void**)&ws.records);
     for (int k = 0; k < 2 && ok; ++k) {
         ok = batch_alloc(b, (size_t)max_blocks * sizeof(uint32_t), (void**)&ws.seg_count[k]) &&
              batch_alloc(b, (size_t)jatam::kSizeBuckets * max_blocks * sizeof(uint32_t),
@@ -373,6 +374,372 @@ const char* jatam_batch_stage_name(int stage)
         "first_run_kernel<16>", "size_sort<16>", "repeat_kernel<16>",
         "first_run_kernel<32>", "size_sort<32>", "repeat_kernel<32>"};
     return stage >= 0 && stage < jatam::kStages ? names[stage] : "";
+}
+
+// ---------------------------------------------------------------------------
+// Genetic algorithm.
+// ---------------------------------------------------------------------------
+static int ga_args(const jatam_ga_params_t* p, int t, int c, int32_t generation,
+                   jatam::GaArgs* g)
+{
+    const int bits = log2_exact(c);
+    if (p == nullptr || bits < 0 || t < 1 || t > 4 || 4 * t * bits > 64 || p->tournament < 1 ||
+        p->tournament > 8 || p->mut_den < 1 || p->mut_num < 0 || p->mut_num > p->mut_den)
+        return JATAM_E_INVALID_ARG;
+    g->key0 = (uint32_t)p->seed;
+    g->key1 = (uint32_t)(p->seed >> 32);
+    g->generation = generation;
+    g->tournament = p->tournament;
+    g->mut_num = p->mut_num;
+    g->mut_den = p->mut_den;
+    g->t = t;
+    g->c = c;
+    g->bits = bits;
+    return JATAM_OK;
+}
+
+int jatam_ga_offspring(const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c,
+                       const jatam_ga_params_t* p, int32_t generation, int64_t n_out,
+                       uint64_t* out, void* stream)
+{
+    jatam::GaArgs g;
+    const int rc = ga_args(p, t, c, generation, &g);
+    if (rc != JATAM_OK)
+        return rc;
+    if (n < 1 || n > (int64_t)0xFFFFFFFFu || n_out < 0 || n_out > (int64_t)0xFFFFFFFFu ||
+        pop == nullptr || fit == nullptr || (n_out > 0 && out == nullptr))
+        return JATAM_E_INVALID_ARG;
+    return jatam::launch_ga_offspring(pop, fit, (uint32_t)n, g, (uint32_t)n_out, out,
+                                      (hipStream_t)stream);
+}
+
+int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit, int64_t n, int t,
+                  int c, int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
+                  int32_t generation, uint64_t* next_pop, int32_t* next_fit, void* stream)
+{
+    jatam::GaArgs g;
+    int rc = ga_args(p, t, c, generation, &g);
+    if (rc != JATAM_OK)
+        return rc;
+    if (batch == nullptr || n < 1 || n > batch->max_n || pop == nullptr || fit == nullptr ||
+        next_pop == nullptr || next_fit == nullptr || next_pop == pop)
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((rc = jatam::launch_ga_offspring(pop, fit, (uint32_t)n, g, (uint32_t)n, next_pop, s)) !=
+        JATAM_OK)
+        return rc;
+    if ((rc = jatam_batch_classify(batch, next_pop, n, t, c, grid_limit, runs, seed,
+                                   batch->ws.records, nullptr, stream)) != JATAM_OK)
+        return rc;
+    return jatam::launch_ga_fitness(batch->ws.records, (uint32_t)n, next_fit, s);
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate MLP.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct jatam_mlp {
+    int device;
+    int64_t max_batch;     // padded to a multiple of 32
+    int step;              // Adam steps taken since the parameters were set
+    jatam::MlpArgs a;
+    void* allocations[16];
+    int nalloc;
+};
+
+static void mlp_views(float* flat, jatam::MlpTensors* t)
+{
+    t->flat = flat;
+    t->w1 = flat + jatam::kMlpOffW1;
+    t->b1 = flat + jatam::kMlpOffB1;
+    t->w2 = flat + jatam::kMlpOffW2;
+    t->b2 = flat + jatam::kMlpOffB2;
+    t->w3 = flat + jatam::kMlpOffW3;
+    t->b3 = flat + jatam::kMlpOffB3;
+}
+
+static void mlp_free(jatam_mlp_t* m)
+{
+    for (int i = 0; i < m->nalloc; ++i)
+        (void)hipFree(m->allocations[i]);
+    delete m;
+}
+
+static bool mlp_alloc(jatam_mlp_t* m, size_t bytes, void** out)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        return false;
+    m->allocations[m->nalloc++] = p;
+    *out = p;
+    return true;
+}
+
+static uint32_t pad32(int64_t n) { return (uint32_t)((n + 31) / 32 * 32); }
+
+extern "C" {
+
+int jatam_mlp_create(int64_t max_batch, int c, jatam_mlp_t** mlp)
+{
+    const int bits = log2_exact(c);
+    if (mlp == nullptr || max_batch < 1 || max_batch > (1 << 24) || bits < 0 || c > 8)
+        return JATAM_E_INVALID_ARG;
+    *mlp = nullptr;
+    jatam_mlp_t* m = new (std::nothrow) jatam_mlp_t();
+    if (m == nullptr)
+        return JATAM_E_HIP;
+    m->nalloc = 0;
+    m->step = 0;
+    m->max_batch = pad32(max_batch);
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return JATAM_E_HIP;
+    }
+    const size_t P = jatam::kMlpParams, B = (size_t)m->max_batch, Hd = jatam::kMlpHidden;
+    float *p, *g;
+    jatam::MlpArgs& a = m->a;
+    bool ok = mlp_alloc(m, P * 4, (void**)&p) && mlp_alloc(m, P * 4, (void**)&g) &&
+              mlp_alloc(m, P * 4, (void**)&a.m) && mlp_alloc(m, P * 4, (void**)&a.v) &&
+              mlp_alloc(m, (size_t)jatam::kMlpIn * Hd * 2, (void**)&a.w1b) &&
+              mlp_alloc(m, Hd * Hd * 2, (void**)&a.w2b) &&
+              mlp_alloc(m, Hd * jatam::kMlpOut * 2, (void**)&a.w3b) &&
+              mlp_alloc(m, B * jatam::kMlpIn * 2, (void**)&a.x) &&
+              mlp_alloc(m, B * Hd * 2, (void**)&a.h1) && mlp_alloc(m, B * Hd * 2, (void**)&a.h2) &&
+              mlp_alloc(m, B * Hd * 2, (void**)&a.dh2) &&
+              mlp_alloc(m, B * Hd * 2, (void**)&a.dh1) &&
+              mlp_alloc(m, B * jatam::kMlpOut * 4, (void**)&a.dout) &&
+              mlp_alloc(m, B * 4, (void**)&a.loss);
+    if (!ok) {
+        mlp_free(m);
+        return JATAM_E_HIP;
+    }
+    mlp_views(p, &a.p);
+    mlp_views(g, &a.g);
+    a.c = c;
+    a.bits = bits;
+    if (jatam::mlp_launch_init(a, 0x5eed, nullptr) != JATAM_OK ||
+        hipDeviceSynchronize() != hipSuccess) {
+        mlp_free(m);
+        return JATAM_E_HIP;
+    }
+    *mlp = m;
+    return JATAM_OK;
+}
+
+int jatam_mlp_destroy(jatam_mlp_t* mlp)
+{
+    if (mlp == nullptr)
+        return JATAM_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    mlp_free(mlp);
+    return e == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+int jatam_mlp_init(jatam_mlp_t* mlp, uint64_t seed, void* stream)
+{
+    if (mlp == nullptr)
+        return JATAM_E_INVALID_ARG;
+    mlp->step = 0;
+    return jatam::mlp_launch_init(mlp->a, seed, (hipStream_t)stream);
+}
+
+int jatam_mlp_set_params(jatam_mlp_t* mlp, const float* params, void* stream)
+{
+    if (mlp == nullptr || params == nullptr)
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)jatam::kMlpParams * 4;
+    if (hipMemcpyAsync(mlp->a.p.flat, params, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemsetAsync(mlp->a.m, 0, bytes, s) != hipSuccess ||
+        hipMemsetAsync(mlp->a.v, 0, bytes, s) != hipSuccess)
+        return JATAM_E_HIP;
+    mlp->step = 0;
+    return jatam::mlp_launch_refresh(mlp->a, s);
+}
+
+int jatam_mlp_get_params(jatam_mlp_t* mlp, float* params, float* grads, void* stream)
+{
+    if (mlp == nullptr)
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)jatam::kMlpParams * 4;
+    if (params != nullptr &&
+        hipMemcpyAsync(params, mlp->a.p.flat, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return JATAM_E_HIP;
+    if (grads != nullptr &&
+        hipMemcpyAsync(grads, mlp->a.g.flat, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return JATAM_E_HIP;
+    return JATAM_OK;
+}
+
+int jatam_mlp_forward(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                      int64_t n, float* out4, void* stream)
+{
+    if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || out4 == nullptr)) ||
+        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    for (int64_t at = 0; at < n; at += mlp->max_batch) {
+        const int64_t k = n - at < mlp->max_batch ? n - at : mlp->max_batch;
+        const int rc = jatam::mlp_launch_forward(mlp->a, genomes + at, t ? t + at : nullptr, t_all,
+                                                 (uint32_t)k, pad32(k), nullptr,
+                                                 out4 + at * jatam::kMlpOut, s);
+        if (rc != JATAM_OK)
+            return rc;
+    }
+    return JATAM_OK;
+}
+
+int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                         const jatam_result_t* labels, int64_t n, float lr, float* loss_out,
+                         void* stream)
+{
+    if (mlp == nullptr || n < 1 || n > mlp->max_batch || genomes == nullptr ||
+        labels == nullptr || !(lr >= 0.f) ||
+        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    int rc = jatam::mlp_launch_forward(mlp->a, genomes, t, t_all, (uint32_t)n, pad32(n), labels,
+                                       nullptr, s);
+    if (rc == JATAM_OK)
+        rc = jatam::mlp_launch_backward(mlp->a, (uint32_t)n, pad32(n), loss_out, s);
+    if (rc == JATAM_OK && lr > 0.f)
+        rc = jatam::mlp_launch_adam(mlp->a, lr, ++mlp->step, s);
+    return rc;
+}
+
+int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                    int64_t n, float* scores, void* stream)
+{
+    if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || scores == nullptr)) ||
+        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    for (int64_t at = 0; at < n; at += mlp->max_batch) {
+        const int64_t k = n - at < mlp->max_batch ? n - at : mlp->max_batch;
+        const int rc = jatam::mlp_launch_score(mlp->a, genomes + at, t ? t + at : nullptr, t_all,
+                                               (uint32_t)k, pad32(k), scores + at, s);
+        if (rc != JATAM_OK)
+            return rc;
+    }
+    return JATAM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Screened GA workspace and top-k selection.
+// ---------------------------------------------------------------------------
+struct jatam_ga {
+    int device;
+    int64_t max_cand;
+    uint64_t* cand;          // offspring candidates
+    float* scores;           // their surrogate scores
+    uint32_t* idx;           // kept candidates
+    jatam::SelectWork sel;
+    void* allocations[8];
+    int nalloc;
+};
+
+static void ga_free(jatam_ga_t* g)
+{
+    for (int i = 0; i < g->nalloc; ++i)
+        (void)hipFree(g->allocations[i]);
+    delete g;
+}
+
+static bool ga_alloc(jatam_ga_t* g, size_t bytes, void** out)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        return false;
+    g->allocations[g->nalloc++] = p;
+    *out = p;
+    return true;
+}
+
+extern "C" {
+
+int jatam_ga_create(int64_t max_candidates, jatam_ga_t** ga)
+{
+    if (ga == nullptr || max_candidates < 1 || max_candidates > (int64_t)0xFFFFFFFFu)
+        return JATAM_E_INVALID_ARG;
+    *ga = nullptr;
+    jatam_ga_t* g = new (std::nothrow) jatam_ga_t();
+    if (g == nullptr)
+        return JATAM_E_HIP;
+    g->nalloc = 0;
+    g->max_cand = max_candidates;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return JATAM_E_HIP;
+    }
+    const size_t n = (size_t)max_candidates;
+    const bool ok = ga_alloc(g, n * 8, (void**)&g->cand) && ga_alloc(g, n * 4, (void**)&g->scores) &&
+                    ga_alloc(g, n * 4, (void**)&g->idx) &&
+                    ga_alloc(g, jatam::kSelectState * 4, (void**)&g->sel.state) &&
+                    ga_alloc(g, n * 4, (void**)&g->sel.flag) &&
+                    ga_alloc(g, n * 4, (void**)&g->sel.rank_eq) &&
+                    ga_alloc(g, n * 4, (void**)&g->sel.pos) &&
+                    ga_alloc(g, (n / 1024 + 2) * 4, (void**)&g->sel.sums);
+    if (!ok) {
+        ga_free(g);
+        return JATAM_E_HIP;
+    }
+    *ga = g;
+    return JATAM_OK;
+}
+
+int jatam_ga_destroy(jatam_ga_t* ga)
+{
+    if (ga == nullptr)
+        return JATAM_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    ga_free(ga);
+    return e == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+int jatam_select_top(jatam_ga_t* ga, const float* scores, int64_t n, int64_t k, uint32_t* out_idx,
+                     void* stream)
+{
+    if (ga == nullptr || scores == nullptr || n < 0 || n > ga->max_cand || k < 0 || k > n ||
+        (k > 0 && out_idx == nullptr))
+        return JATAM_E_INVALID_ARG;
+    return jatam::launch_select_top(scores, (uint32_t)n, (uint32_t)k, out_idx, ga->sel,
+                                    (hipStream_t)stream);
+}
+
+int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* mlp,
+                           const uint64_t* pop, const int32_t* fit, int64_t n, int t, int c,
+                           int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
+                           int32_t generation, int oversample, uint64_t* next_pop,
+                           int32_t* next_fit, void* stream)
+{
+    jatam::GaArgs g;
+    int rc = ga_args(p, t, c, generation, &g);
+    if (rc != JATAM_OK)
+        return rc;
+    if (ga == nullptr || batch == nullptr || mlp == nullptr || n < 1 || oversample < 1 ||
+        n * oversample > ga->max_cand || n > batch->max_n || pop == nullptr || fit == nullptr ||
+        next_pop == nullptr || next_fit == nullptr || next_pop == pop || t > 3 ||
+        c != (1 << mlp->a.bits))
+        return JATAM_E_INVALID_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    const uint32_t m = (uint32_t)(n * oversample);
+    if ((rc = jatam::launch_ga_offspring(pop, fit, (uint32_t)n, g, m, ga->cand, s)) != JATAM_OK)
+        return rc;
+    if ((rc = jatam_mlp_score(mlp, ga->cand, nullptr, t, m, ga->scores, stream)) != JATAM_OK)
+        return rc;
+    if ((rc = jatam::launch_select_top(ga->scores, m, (uint32_t)n, ga->idx, ga->sel, s)) !=
+        JATAM_OK)
+        return rc;
+    if ((rc = jatam::launch_gather(ga->cand, ga->idx, (uint32_t)n, next_pop, s)) != JATAM_OK)
+        return rc;
+    if ((rc = jatam_batch_classify(batch, next_pop, n, t, c, grid_limit, runs, seed,
+                                   batch->ws.records, nullptr, stream)) != JATAM_OK)
+        return rc;
+    return jatam::launch_ga_fitness(batch->ws.records, (uint32_t)n, next_fit, s);
 }
 
 }  // extern "C"

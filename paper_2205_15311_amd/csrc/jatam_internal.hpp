@@ -43,6 +43,7 @@ struct DeviceWorkspace {
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
     uint32_t* small_hash;     // [2]: D4 hash of the monomer and of the domino
+    jatam_result_t* records;  // [max_n] records of a GA generation
 };
 
 struct BatchArgs {
@@ -75,5 +76,88 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
 void batch_persistent_blocks(int cus, int blocks[2][2]);
 int launch_batched(const BatchArgs& a, const bool classes[2], const int blocks[2][2], int tm,
                    hipStream_t stream, hipEvent_t* marks, uint8_t* launched);
+
+// ---------------------------------------------------------------------------
+// Genetic algorithm.
+// ---------------------------------------------------------------------------
+struct GaArgs {
+    uint32_t key0, key1;   // Philox key = GA seed
+    int32_t generation;
+    int tournament;        // T
+    int mut_num, mut_den;  // per-edge mutation probability
+    int t, c, bits;
+};
+
+int launch_ga_offspring(const uint64_t* pop, const int32_t* fit, uint32_t n, const GaArgs& g,
+                        uint32_t n_out, uint64_t* out, hipStream_t stream);
+int launch_ga_fitness(const jatam_result_t* rec, uint32_t n, int32_t* fit, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Surrogate MLP: 96 -> 256 -> 256 -> 4.  Flat fp32 parameter order:
+// w1 [96][256], b1 [256], w2 [256][256], b2 [256], w3 [256][4], b3 [4].
+// ---------------------------------------------------------------------------
+constexpr int kMlpEdges = 12, kMlpIn = 96, kMlpHidden = 256, kMlpOut = 4;
+constexpr int kMlpOffW1 = 0;
+constexpr int kMlpOffB1 = kMlpOffW1 + kMlpIn * kMlpHidden;
+constexpr int kMlpOffW2 = kMlpOffB1 + kMlpHidden;
+constexpr int kMlpOffB2 = kMlpOffW2 + kMlpHidden * kMlpHidden;
+constexpr int kMlpOffW3 = kMlpOffB2 + kMlpHidden;
+constexpr int kMlpOffB3 = kMlpOffW3 + kMlpHidden * kMlpOut;
+constexpr int kMlpParams = kMlpOffB3 + kMlpOut;   // 91,652
+
+struct MlpTensors {      // views into one flat fp32 vector
+    float* flat;
+    float *w1, *b1, *w2, *b2, *w3, *b3;
+};
+
+struct MlpArgs {
+    MlpTensors p;        // fp32 master weights
+    MlpTensors g;        // gradients of the last training step
+    float* m;            // Adam first moments
+    float* v;            // Adam second moments
+    uint16_t* w1b;       // bf16 copies of the weights
+    uint16_t* w2b;
+    uint16_t* w3b;
+    uint16_t* x;         // [batch][96] one-hot inputs (bf16)
+    uint16_t* h1;        // [batch][256] bf16
+    uint16_t* h2;        // [batch][256] bf16
+    uint16_t* dh2;       // [batch][256] bf16
+    uint16_t* dh1;       // [batch][256] bf16
+    float* dout;         // [batch][4]
+    float* loss;         // [batch] per-sample loss
+    int c, bits;
+};
+
+int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s);
+int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
+                     uint32_t n, uint32_t n_pad, float* scores, hipStream_t s);
+int mlp_launch_refresh(const MlpArgs& a, hipStream_t s);
+int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
+                       uint32_t n, uint32_t n_pad, const jatam_result_t* labels, float* out4,
+                       hipStream_t s);
+int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* loss_out,
+                        hipStream_t s);
+int mlp_launch_adam(const MlpArgs& a, float lr, int step, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Top-k selection (jatam_select.hip).
+// ---------------------------------------------------------------------------
+constexpr int kSelectState = 2 + 256;
+
+struct SelectWork {
+    uint32_t* state;     // [kSelectState]
+    uint32_t* flag;      // [n]
+    uint32_t* rank_eq;   // [n]
+    uint32_t* pos;       // [n]
+    uint32_t* sums;      // [n / 1024 + 1]
+};
+
+// Indices of the k best scores (descending, ties to the lower index, NaN
+// last), in ascending index order, into out_idx[k].
+int launch_select_top(const float* scores, uint32_t n, uint32_t k, uint32_t* out_idx,
+                      const SelectWork& w, hipStream_t s);
+
+int launch_gather(const uint64_t* src, const uint32_t* idx, uint32_t n, uint64_t* dst,
+                  hipStream_t s);
 
 }  // namespace jatam

@@ -1,0 +1,469 @@
+// jatam_mlp.hip - the surrogate MLP: training and inference on gfx950.
+//
+// Not from the paper (which has no learned part): the surrogate predicts a
+// genotype's class (UNBOUND / ND / DET) and log(1 + size) from its edge
+// colours, so the batched path can order work and the GA can screen
+// offspring; every reported class still comes from exact assembly.
+//
+// x = one-hot of the 12 edge colours (12 x 8; absent tiles all zero)
+// h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2) (256 wide), out = h2 W3 + b3.
+// Loss = mean cross-entropy of the 3 class logits + mean squared error of
+// log1p(size).  Weights are kept in fp32 (with Adam moments) and used as
+// bf16; h1, h2 and the hidden gradients are stored as bf16; every product
+// accumulates in fp32.
+//
+//   layer 1      a gather: the sum of 4t rows of W1 (a one-hot input times a
+//                matrix is no work for a matrix core)
+//   h1 W2, dh2 W2^T, h1^T dh2, x^T dh1
+//                bf16 MFMA GEMMs (v_mfma_f32_16x16x32_bf16), one wave per
+//                16 x 16 output tile, fused bias/ReLU/mask epilogues
+//   head, loss   per-sample dot products of length 256 and a softmax
+//   Adam         elementwise over the 91,652 fp32 parameters
+#include "jatam_device.hpp"
+#include "jatam_internal.hpp"
+
+namespace jatam {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+// fp32 -> bf16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u)
+        return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Keeps the bf16 copy of weight i (flat index) equal to its fp32 master.
+__device__ __forceinline__ void refresh_bf16(const MlpArgs& a, int i, float w)
+{
+    if (i < kMlpOffB1)
+        a.w1b[i] = bf16_bits(w);
+    else if (i >= kMlpOffW2 && i < kMlpOffB2)
+        a.w2b[i - kMlpOffW2] = bf16_bits(w);
+    else if (i >= kMlpOffW3 && i < kMlpOffB3)
+        a.w3b[i - kMlpOffW3] = bf16_bits(w);
+}
+
+// ---------------------------------------------------------------------------
+// Layer 1: h1 = bf16(relu(sum of W1 rows + b1)); also the one-hot x (bf16).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mlp_layer1_kernel(MlpArgs a, const uint64_t* genomes,
+                                                         const uint8_t* tvec, int t_all,
+                                                         uint32_t n)
+{
+    const uint32_t b = blockIdx.x;          // sample (rows n..gridDim.x-1 are padding)
+    const int j = threadIdx.x;              // hidden unit
+    if (b >= n) {
+        a.h1[(size_t)b * kMlpHidden + j] = 0;
+        if (j < kMlpIn)
+            a.x[(size_t)b * kMlpIn + j] = 0;
+        return;
+    }
+    const uint64_t g = genomes[b];
+    const int t = tvec != nullptr ? tvec[b] : t_all;
+    const uint32_t cmask = (uint32_t)a.c - 1u;
+    float acc = 0.f;
+    for (int e = 0; e < kMlpEdges; ++e) {
+        if (e >= 4 * t)
+            break;
+        const uint32_t colour = (uint32_t)(g >> (a.bits * (4 * t - 1 - e))) & cmask;
+        acc += bf16_float(a.w1b[(e * 8 + colour) * kMlpHidden + j]);
+    }
+    acc += a.p.b1[j];
+    a.h1[(size_t)b * kMlpHidden + j] = bf16_bits(acc > 0.f ? acc : 0.f);   // +0, never -0
+    if (j < kMlpIn) {
+        const int e = j >> 3;
+        uint32_t hot = 0;
+        if (e < 4 * t)
+            hot = ((uint32_t)(g >> (a.bits * (4 * t - 1 - e))) & cmask) == (uint32_t)(j & 7);
+        a.x[(size_t)b * kMlpIn + j] = hot ? (uint16_t)0x3F80u : (uint16_t)0;   // 1.0 or 0.0
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M x N] = sum_k A(m, k) B(k, n), bf16 operands addressed by strides
+// (so transposes cost nothing), fp32 accumulation in v_mfma_f32_16x16x32_bf16.
+// One wave computes one 16 x 16 tile; K is a multiple of 32.
+//
+// Operand layout of the 16x16x32 MFMA (one wave): lane l holds
+//   A[l % 16][8 * (l / 16) + i], i < 8      (16 x 32, M x K)
+//   B[8 * (l / 16) + i][l % 16], i < 8      (32 x 16, K x N)
+// and receives D[4 * (l / 16) + i][l % 16], i < 4.
+// ---------------------------------------------------------------------------
+enum { kEpStoreF32 = 0, kEpBiasRelu = 1, kEpReluMask = 2 };
+
+struct GemmArgs {
+    const uint16_t* A;
+    int64_t sam, sak;        // A(m, k) = A[m * sam + k * sak]
+    const uint16_t* B;
+    int64_t sbk, sbn;        // B(k, n) = B[k * sbk + n * sbn]
+    int M, N, K;
+    int epilogue;
+    float* C32;              // kEpStoreF32: C[m * N + n]
+    uint16_t* C16;           // kEpBiasRelu / kEpReluMask: bf16 C[m * N + n]
+    const float* bias;       // kEpBiasRelu: bias[n]
+    const uint16_t* mask;    // kEpReluMask: keep where mask[m * N + n] > 0
+};
+
+__device__ __forceinline__ int lane16() { return (int)(__lane_id() & 15); }
+__device__ __forceinline__ int quad() { return (int)(__lane_id() >> 4); }
+
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
+{
+    const int wave = (int)(threadIdx.x >> 6);
+    const int tiles_n = g.N / 16;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= (g.M / 16) * tiles_n)
+        return;
+    const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
+    const int r = lane16(), q = quad();
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        bf16x8 av, bv;
+        const int kq = k0 + 8 * q;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint16_t ab = g.A[(int64_t)(m0 + r) * g.sam + (int64_t)(kq + i) * g.sak];
+            const uint16_t bb = g.B[(int64_t)(kq + i) * g.sbk + (int64_t)(n0 + r) * g.sbn];
+            av[i] = __builtin_bit_cast(__bf16, ab);
+            bv[i] = __builtin_bit_cast(__bf16, bb);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + 4 * q + i, n = n0 + r;
+        const float v = acc[i];
+        const int64_t o = (int64_t)m * g.N + n;
+        if (g.epilogue == kEpStoreF32) {
+            g.C32[o] = v;
+        } else if (g.epilogue == kEpBiasRelu) {
+            const float z = v + g.bias[n];
+            g.C16[o] = bf16_bits(z > 0.f ? z : 0.f);
+        } else {
+            g.C16[o] = bf16_bits(g.mask[o] != 0 ? v : 0.f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Head and loss: out = h2 W3 + b3 per sample; with labels, the per-sample loss
+// and dout = d(mean loss)/d(out).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void mlp_head_kernel(MlpArgs a, uint32_t n,
+                                                       const jatam_result_t* labels,
+                                                       float* out4, float* scores)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= n)
+        return;
+    float o[kMlpOut];
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k)
+        o[k] = a.p.b3[k];
+    const uint16_t* h = a.h2 + (size_t)b * kMlpHidden;
+    for (int j = 0; j < kMlpHidden; ++j) {
+        const float hj = bf16_float(h[j]);
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k)
+            o[k] = fmaf(hj, bf16_float(a.w3b[j * kMlpOut + k]), o[k]);
+    }
+    if (out4 != nullptr)
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k)
+            out4[(size_t)b * kMlpOut + k] = o[k];
+    if (scores != nullptr) {
+        // expected size of a deterministic structure: P(DET) e^pred - 1
+        const float mx = fmaxf(o[0], fmaxf(o[1], o[2]));
+        const float e0 = expf(o[0] - mx), e1 = expf(o[1] - mx), e2 = expf(o[2] - mx);
+        scores[b] = e2 / (e0 + e1 + e2) * expf(o[3]) - 1.f;
+    }
+    if (labels == nullptr)
+        return;
+    const jatam_result_t rec = labels[b];
+    const int y = rec.cls == JATAM_UNBOUND ? 0 : rec.cls == JATAM_DET ? 2 : 1;
+    const float mx = fmaxf(o[0], fmaxf(o[1], o[2]));
+    const float e0 = expf(o[0] - mx), e1 = expf(o[1] - mx), e2 = expf(o[2] - mx);
+    const float s = e0 + e1 + e2;
+    const float py = (y == 0 ? e0 : y == 1 ? e1 : e2) / s;
+    const float target = log1pf((float)rec.size);
+    const float err = o[3] - target;
+    a.loss[b] = -logf(py) + err * err;
+    const float inv = 1.f / (float)n;
+    a.dout[(size_t)b * kMlpOut + 0] = (e0 / s - (y == 0 ? 1.f : 0.f)) * inv;
+    a.dout[(size_t)b * kMlpOut + 1] = (e1 / s - (y == 1 ? 1.f : 0.f)) * inv;
+    a.dout[(size_t)b * kMlpOut + 2] = (e2 / s - (y == 2 ? 1.f : 0.f)) * inv;
+    a.dout[(size_t)b * kMlpOut + 3] = 2.f * err * inv;
+}
+
+// dh2 = bf16((dout W3^T) * (h2 > 0)), one thread per (sample, unit); zero on
+// padding rows (b >= n).
+__global__ __launch_bounds__(256) void mlp_dh2_kernel(MlpArgs a, uint32_t n)
+{
+    const uint32_t b = blockIdx.x;
+    const int j = threadIdx.x;
+    if (b >= n) {
+        a.dh2[(size_t)b * kMlpHidden + j] = 0;
+        return;
+    }
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k)
+        v = fmaf(a.dout[(size_t)b * kMlpOut + k], bf16_float(a.w3b[j * kMlpOut + k]), v);
+    const size_t o = (size_t)b * kMlpHidden + j;
+    a.dh2[o] = bf16_bits(a.h2[o] != 0 ? v : 0.f);
+}
+
+// Column sums: out[j] = sum_b src[b][j] (bf16 or fp32 rows), deterministic.
+__global__ __launch_bounds__(256) void mlp_colsum_kernel(const uint16_t* src16, const float* src32,
+                                                         uint32_t n, int cols, float* out)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= cols)
+        return;
+    float s = 0.f;
+    for (uint32_t b = 0; b < n; ++b)
+        s += src16 != nullptr ? bf16_float(src16[(size_t)b * cols + j])
+                              : src32[(size_t)b * cols + j];
+    out[j] = s;
+}
+
+// dW3[j][k] = sum_b h2[b][j] dout[b][k].
+__global__ __launch_bounds__(256) void mlp_dw3_kernel(MlpArgs a, uint32_t n)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= kMlpHidden * kMlpOut)
+        return;
+    const int j = idx / kMlpOut, k = idx % kMlpOut;
+    float s = 0.f;
+    for (uint32_t b = 0; b < n; ++b)
+        s = fmaf(bf16_float(a.h2[(size_t)b * kMlpHidden + j]), a.dout[(size_t)b * kMlpOut + k], s);
+    a.g.w3[idx] = s;
+}
+
+// Mean loss of the batch (one block, fixed order).
+__global__ __launch_bounds__(256) void mlp_loss_kernel(MlpArgs a, uint32_t n, float* loss_out)
+{
+    __shared__ float part[256];
+    float s = 0.f;
+    for (uint32_t b = threadIdx.x; b < n; b += 256)
+        s += a.loss[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss_out != nullptr)
+        loss_out[0] = part[0] / (float)n;
+}
+
+// Adam on the flat fp32 parameter vector; refreshes the bf16 weight copies.
+__global__ __launch_bounds__(256) void mlp_adam_kernel(MlpArgs a, float lr, float bc1, float bc2)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kMlpParams)
+        return;
+    const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+    const float gi = a.g.flat[i];
+    const float m = beta1 * a.m[i] + (1.f - beta1) * gi;
+    const float v = beta2 * a.v[i] + (1.f - beta2) * gi * gi;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float w = a.p.flat[i] - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+    a.p.flat[i] = w;
+    refresh_bf16(a, i, w);
+}
+
+// bf16 copies of all weights from the fp32 masters.
+__global__ __launch_bounds__(256) void mlp_refresh_kernel(MlpArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < kMlpParams)
+        refresh_bf16(a, i, a.p.flat[i]);
+}
+
+// The library's own initialisation: He-uniform weights from Philox words,
+// w = (2u - 1) sqrt(6 / fan_in) with u = word / 2^32; biases zero.
+__global__ __launch_bounds__(256) void mlp_init_kernel(MlpArgs a, uint32_t k0, uint32_t k1)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kMlpParams)
+        return;
+    float w = 0.f;
+    int fan_in = 0;
+    if (i < kMlpOffB1)
+        fan_in = kMlpIn;
+    else if (i >= kMlpOffW2 && i < kMlpOffB2)
+        fan_in = kMlpHidden;
+    else if (i >= kMlpOffW3 && i < kMlpOffB3)
+        fan_in = kMlpHidden;
+    if (fan_in) {
+        const Words4 r = philox4x32_10((uint32_t)i, 0, 0, 3u << 28, k0, k1);
+        const float u = (float)(r.w[0] >> 8) * (1.f / 16777216.f);
+        w = (2.f * u - 1.f) * sqrtf(6.f / (float)fan_in);
+    }
+    a.p.flat[i] = w;
+    a.m[i] = 0.f;
+    a.v[i] = 0.f;
+    refresh_bf16(a, i, w);
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+static int gemm(const GemmArgs& g, hipStream_t s)
+{
+    const int tiles = (g.M / 16) * (g.N / 16);
+    hipLaunchKernelGGL(mlp_gemm_kernel, dim3((tiles + 3) / 4), dim3(256), 0, s, g);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_init_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a,
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+int mlp_launch_refresh(const MlpArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_refresh_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+// Forward pass over n samples (n a multiple of 16); out4 may be null.
+// Forward pass over n samples padded to n_pad (a multiple of 32): padding rows
+// carry zero inputs and are never read back; out4 may be null.
+int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
+                       uint32_t n, uint32_t n_pad, const jatam_result_t* labels, float* out4,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_layer1_kernel, dim3(n_pad), dim3(256), 0, s, a, genomes, tvec, t_all,
+                       n);
+    GemmArgs g{};
+    g.A = a.h1;
+    g.sam = kMlpHidden;
+    g.sak = 1;
+    g.B = a.w2b;
+    g.sbk = kMlpHidden;
+    g.sbn = 1;
+    g.M = (int)n_pad;
+    g.N = kMlpHidden;
+    g.K = kMlpHidden;
+    g.epilogue = kEpBiasRelu;
+    g.C16 = a.h2;
+    g.bias = a.p.b2;
+    int rc = gemm(g, s);
+    if (rc != JATAM_OK)
+        return rc;
+    hipLaunchKernelGGL(mlp_head_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n, labels,
+                       out4, (float*)nullptr);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+// Forward pass writing only the screening score of each sample.
+int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
+                     uint32_t n, uint32_t n_pad, float* scores, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_layer1_kernel, dim3(n_pad), dim3(256), 0, s, a, genomes, tvec, t_all,
+                       n);
+    GemmArgs g{};
+    g.A = a.h1;
+    g.sam = kMlpHidden;
+    g.sak = 1;
+    g.B = a.w2b;
+    g.sbk = kMlpHidden;
+    g.sbn = 1;
+    g.M = (int)n_pad;
+    g.N = kMlpHidden;
+    g.K = kMlpHidden;
+    g.epilogue = kEpBiasRelu;
+    g.C16 = a.h2;
+    g.bias = a.p.b2;
+    int rc = gemm(g, s);
+    if (rc != JATAM_OK)
+        return rc;
+    hipLaunchKernelGGL(mlp_head_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n,
+                       (const jatam_result_t*)nullptr, (float*)nullptr, scores);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+// Backward pass of the last forward (with labels).
+int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* loss_out,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(256), 0, s, a, n, loss_out);
+    hipLaunchKernelGGL(mlp_dw3_kernel, dim3((kMlpHidden * kMlpOut + 255) / 256), dim3(256), 0, s,
+                       a, n);
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)nullptr,
+                       (const float*)a.dout, n, kMlpOut, a.g.b3);
+    hipLaunchKernelGGL(mlp_dh2_kernel, dim3(n_pad), dim3(256), 0, s, a, n);
+    // dW2 = h1^T dh2 (M = K_hidden rows of h1^T, K = batch)
+    GemmArgs g{};
+    g.A = a.h1;
+    g.sam = 1;
+    g.sak = kMlpHidden;
+    g.B = a.dh2;
+    g.sbk = kMlpHidden;
+    g.sbn = 1;
+    g.M = kMlpHidden;
+    g.N = kMlpHidden;
+    g.K = (int)n_pad;
+    g.epilogue = kEpStoreF32;
+    g.C32 = a.g.w2;
+    int rc = gemm(g, s);
+    if (rc != JATAM_OK)
+        return rc;
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)a.dh2,
+                       (const float*)nullptr, n_pad, kMlpHidden, a.g.b2);
+    // dh1 = bf16((dh2 W2^T) * (h1 > 0))
+    g = GemmArgs{};
+    g.A = a.dh2;
+    g.sam = kMlpHidden;
+    g.sak = 1;
+    g.B = a.w2b;
+    g.sbk = 1;
+    g.sbn = kMlpHidden;
+    g.M = (int)n_pad;
+    g.N = kMlpHidden;
+    g.K = kMlpHidden;
+    g.epilogue = kEpReluMask;
+    g.C16 = a.dh1;
+    g.mask = a.h1;
+    if ((rc = gemm(g, s)) != JATAM_OK)
+        return rc;
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)a.dh1,
+                       (const float*)nullptr, n_pad, kMlpHidden, a.g.b1);
+    // dW1 = x^T dh1
+    g = GemmArgs{};
+    g.A = a.x;
+    g.sam = 1;
+    g.sak = kMlpIn;
+    g.B = a.dh1;
+    g.sbk = kMlpHidden;
+    g.sbn = 1;
+    g.M = kMlpIn;
+    g.N = kMlpHidden;
+    g.K = (int)n_pad;
+    g.epilogue = kEpStoreF32;
+    g.C32 = a.g.w1;
+    return gemm(g, s);
+}
+
+int mlp_launch_adam(const MlpArgs& a, float lr, int step, hipStream_t s)
+{
+    const float bc1 = 1.f - powf(0.9f, (float)step);
+    const float bc2 = 1.f - powf(0.999f, (float)step);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, a, lr,
+                       bc1, bc2);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+}  // namespace jatam

@@ -60,6 +60,36 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_classify_range.restype = i32
         L.jatam_batch_classify_items.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp]
         L.jatam_batch_classify_items.restype = i32
+        L.jatam_ga_offspring.argtypes = [vp, vp, i64, i32, i32, vp, ctypes.c_int32, i64, vp, vp]
+        L.jatam_ga_offspring.restype = i32
+        L.jatam_ga_step.argtypes = [vp, vp, vp, i64, i32, i32, i32, i32, u64, vp,
+                                    ctypes.c_int32, vp, vp, vp]
+        L.jatam_ga_step.restype = i32
+        L.jatam_mlp_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
+        L.jatam_mlp_create.restype = i32
+        L.jatam_mlp_destroy.argtypes = [vp]
+        L.jatam_mlp_destroy.restype = i32
+        L.jatam_mlp_init.argtypes = [vp, u64, vp]
+        L.jatam_mlp_init.restype = i32
+        L.jatam_mlp_set_params.argtypes = [vp, vp, vp]
+        L.jatam_mlp_set_params.restype = i32
+        L.jatam_mlp_get_params.argtypes = [vp, vp, vp, vp]
+        L.jatam_mlp_get_params.restype = i32
+        L.jatam_mlp_forward.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+        L.jatam_mlp_forward.restype = i32
+        L.jatam_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, i64, ctypes.c_float, vp, vp]
+        L.jatam_mlp_train_step.restype = i32
+        L.jatam_mlp_score.argtypes = [vp, vp, vp, i32, i64, vp, vp]
+        L.jatam_mlp_score.restype = i32
+        L.jatam_ga_create.argtypes = [i64, ctypes.POINTER(vp)]
+        L.jatam_ga_create.restype = i32
+        L.jatam_ga_destroy.argtypes = [vp]
+        L.jatam_ga_destroy.restype = i32
+        L.jatam_select_top.argtypes = [vp, vp, i64, i64, vp, vp]
+        L.jatam_select_top.restype = i32
+        L.jatam_ga_step_screened.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, i32, i32, u64, vp,
+                                             ctypes.c_int32, i32, vp, vp, vp]
+        L.jatam_ga_step_screened.restype = i32
         L.jatam_batch_set_refill.argtypes = [vp, i32]
         L.jatam_batch_set_refill.restype = i32
         L.jatam_batch_set_timing.argtypes = [vp, i32]
@@ -131,6 +161,40 @@ def records_to_numpy(rec: torch.Tensor):
     import numpy as np
     dt = np.dtype([("cls", "<i4"), ("size", "<i4"), ("hash", "<u4"), ("steps", "<i4")])
     return rec.detach().cpu().contiguous().numpy().view(dt).reshape(-1)
+
+
+class GAParams(ctypes.Structure):
+    """jatam_ga_params_t."""
+    _fields_ = [("seed", ctypes.c_uint64), ("tournament", ctypes.c_int32),
+                ("mut_num", ctypes.c_int32), ("mut_den", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+    def __init__(self, seed=5, tournament=4, mut_num=1, mut_den=12):
+        super().__init__(seed, tournament, mut_num, mut_den, 0)
+
+
+def _check_pop(pop, fit):
+    if pop.dtype not in (torch.int64, torch.uint64) or pop.dim() != 1 or not pop.is_cuda:
+        raise ValueError("pop must be a 1-D int64/uint64 device tensor")
+    if fit.dtype != torch.int32 or fit.shape != pop.shape or not fit.is_cuda:
+        raise ValueError("fit must be an int32 device tensor shaped like pop")
+    if not pop.is_contiguous() or not fit.is_contiguous():
+        raise ValueError("pop and fit must be contiguous")
+
+
+def ga_offspring(pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
+                 generation: int, c: int = 8, n_out: int | None = None,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """jatam_ga_offspring: n_out offspring genomes (int64 tensor)."""
+    _check_pop(pop, fit)
+    n_out = pop.shape[0] if n_out is None else n_out
+    if out is None:
+        out = torch.empty(n_out, dtype=torch.int64, device=pop.device)
+    rc = lib().jatam_ga_offspring(pop.data_ptr(), fit.data_ptr(), pop.shape[0], t, c,
+                                  ctypes.byref(params), generation, n_out, out.data_ptr(),
+                                  _stream_handle(stream))
+    _check(rc, "jatam_ga_offspring")
+    return out
 
 
 # jatam_item_t: uint64 genome, uint64 rng_id, uint8 t, uint8 grid, 6 pad bytes
@@ -236,6 +300,22 @@ class Batch:
         _check(rc, "jatam_batch_classify_items")
         return rec
 
+    def ga_step(self, pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
+                generation: int, c: int = 8, grid_limit: int = 32, runs: int = 20,
+                seed: int = 1, next_pop: torch.Tensor | None = None,
+                next_fit: torch.Tensor | None = None, stream=None):
+        """jatam_ga_step: (next_pop, next_fit) of one generation."""
+        _check_pop(pop, fit)
+        if next_pop is None:
+            next_pop = torch.empty_like(pop)
+        if next_fit is None:
+            next_fit = torch.empty_like(fit)
+        rc = lib().jatam_ga_step(self._h, pop.data_ptr(), fit.data_ptr(), pop.shape[0], t, c,
+                                 grid_limit, runs, seed, ctypes.byref(params), generation,
+                                 next_pop.data_ptr(), next_fit.data_ptr(), _stream_handle(stream))
+        _check(rc, "jatam_ga_step")
+        return next_pop, next_fit
+
     def set_refill(self, idle_lanes: int) -> None:
         _check(lib().jatam_batch_set_refill(self._h, idle_lanes), "jatam_batch_set_refill")
 
@@ -252,3 +332,139 @@ class Batch:
             raise JatamError(k, "jatam_batch_stage_times")
         return {lib().jatam_batch_stage_name(s).decode(): (ms[s], calls[s]) for s in range(k)
                 if calls[s] > 0}
+
+
+MLP_PARAMS = 91652
+
+
+class MLP:
+    """jatam_mlp_t: the surrogate network, trained and evaluated on the GPU."""
+
+    def __init__(self, max_batch: int = 4096, c: int = 8):
+        handle = ctypes.c_void_p()
+        _check(lib().jatam_mlp_create(int(max_batch), c, ctypes.byref(handle)), "jatam_mlp_create")
+        self._h = handle
+        self.max_batch = int(max_batch)
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().jatam_mlp_destroy(self._h), "jatam_mlp_destroy")
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, seed: int, stream=None) -> None:
+        _check(lib().jatam_mlp_init(self._h, seed, _stream_handle(stream)), "jatam_mlp_init")
+
+    def set_params(self, params: torch.Tensor, stream=None) -> None:
+        if params.dtype != torch.float32 or params.numel() != MLP_PARAMS or not params.is_cuda:
+            raise ValueError("params must be a device float32 tensor of 91652 values")
+        _check(lib().jatam_mlp_set_params(self._h, params.contiguous().data_ptr(),
+                                          _stream_handle(stream)), "jatam_mlp_set_params")
+
+    def get_params(self, grads: bool = False, stream=None):
+        """(params, grads or None) as device float32 tensors."""
+        p = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        g = torch.empty_like(p) if grads else None
+        _check(lib().jatam_mlp_get_params(self._h, p.data_ptr(), g.data_ptr() if grads else None,
+                                          _stream_handle(stream)), "jatam_mlp_get_params")
+        return p, g
+
+    @staticmethod
+    def _tiles(t, n):
+        if isinstance(t, int):
+            return None, t
+        if t.dtype != torch.uint8 or t.shape[0] != n or not t.is_cuda:
+            raise ValueError("t must be an int or a device uint8 tensor of length n")
+        return t.contiguous().data_ptr(), 0
+
+    def forward(self, genomes: torch.Tensor, t, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        n = genomes.shape[0]
+        tp, ta = self._tiles(t, n)
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=genomes.device)
+        _check(lib().jatam_mlp_forward(self._h, genomes.data_ptr(), tp, ta, n, out.data_ptr(),
+                                       _stream_handle(stream)), "jatam_mlp_forward")
+        return out
+
+    def score(self, genomes: torch.Tensor, t, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        """jatam_mlp_score: P(DET) * exp(predicted log1p size) - 1 per genome."""
+        n = genomes.shape[0]
+        tp, ta = self._tiles(t, n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=genomes.device)
+        _check(lib().jatam_mlp_score(self._h, genomes.data_ptr(), tp, ta, n, out.data_ptr(),
+                                     _stream_handle(stream)), "jatam_mlp_score")
+        return out
+
+    def train_step(self, genomes: torch.Tensor, t, labels: torch.Tensor, lr: float = 1e-3,
+                   loss: torch.Tensor | None = None, stream=None):
+        """labels: (n, 4) int32 records of the genomes."""
+        n = genomes.shape[0]
+        tp, ta = self._tiles(t, n)
+        _check(lib().jatam_mlp_train_step(self._h, genomes.data_ptr(), tp, ta,
+                                          labels.data_ptr(), n, float(lr),
+                                          loss.data_ptr() if loss is not None else None,
+                                          _stream_handle(stream)), "jatam_mlp_train_step")
+        return loss
+
+
+class GA:
+    """jatam_ga_t: workspace of the surrogate-screened GA (and top-k select)."""
+
+    def __init__(self, max_candidates: int):
+        handle = ctypes.c_void_p()
+        _check(lib().jatam_ga_create(int(max_candidates), ctypes.byref(handle)), "jatam_ga_create")
+        self._h = handle
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().jatam_ga_destroy(self._h), "jatam_ga_destroy")
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def select_top(self, scores: torch.Tensor, k: int, stream=None) -> torch.Tensor:
+        """Indices (int32 tensor, ascending) of the k best scores."""
+        if scores.dtype != torch.float32 or not scores.is_cuda or not scores.is_contiguous():
+            raise ValueError("scores must be a contiguous device float32 tensor")
+        out = torch.empty(k, dtype=torch.int32, device=scores.device)
+        _check(lib().jatam_select_top(self._h, scores.data_ptr(), scores.shape[0], k,
+                                      out.data_ptr(), _stream_handle(stream)), "jatam_select_top")
+        return out
+
+    def step_screened(self, batch: "Batch", mlp: "MLP", pop: torch.Tensor, fit: torch.Tensor,
+                      t: int, params: GAParams, generation: int, oversample: int = 4, c: int = 8,
+                      grid_limit: int = 32, runs: int = 20, seed: int = 1, stream=None):
+        """jatam_ga_step_screened: (next_pop, next_fit)."""
+        _check_pop(pop, fit)
+        next_pop, next_fit = torch.empty_like(pop), torch.empty_like(fit)
+        rc = lib().jatam_ga_step_screened(self._h, batch._h, mlp._h, pop.data_ptr(),
+                                          fit.data_ptr(), pop.shape[0], t, c, grid_limit, runs,
+                                          seed, ctypes.byref(params), generation, oversample,
+                                          next_pop.data_ptr(), next_fit.data_ptr(),
+                                          _stream_handle(stream))
+        _check(rc, "jatam_ga_step_screened")
+        return next_pop, next_fit

@@ -1,0 +1,120 @@
+"""The surrogate MLP on the GPU against the reference network (oracle/
+mlp_ref.py, fp64 with the same bf16 rounding points).
+
+Tolerances: every product accumulates in fp32 on the GPU and exactly in the
+reference, and the four bf16 roundings (h1, h2, dh2, dh1) can land on
+different sides of a rounding boundary when the fp32 and fp64 sums differ by
+a few fp32 ulps (a fraction ~1e-4 of the elements, each then 1 bf16 ulp =
+2^-8 off).  The forward output is therefore compared to 1e-2 of its scale,
+each gradient tensor to 2% in relative Frobenius norm, and Adam steps (which
+normalise the gradient) elementwise where the gradient is well determined.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def jt():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    import paper_2205_15311_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def sample(n, seed):
+    rng = np.random.default_rng(seed)
+    t = rng.integers(1, 4, size=n)
+    g = rng.integers(0, 1 << 36, size=n, dtype=np.uint64) >> (36 - 12 * t).astype(np.uint64)
+    cls = rng.integers(0, 4, size=n).astype(np.int32)
+    size = rng.integers(1, 80, size=n).astype(np.int32)
+    return g, t, cls, size
+
+
+def to_dev(g, t, cls=None, size=None):
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    dt = torch.from_numpy(t.astype(np.uint8)).cuda()
+    if cls is None:
+        return dg, dt
+    rec = np.zeros((len(g), 4), dtype=np.int32)
+    rec[:, 0], rec[:, 1] = cls, size
+    return dg, dt, torch.from_numpy(rec).cuda()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def test_forward_matches_reference(jt):
+    p = M.random_params(3)
+    g, t, _, _ = sample(1000, 1)
+    with jt.MLP(4096) as net:
+        net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
+        dg, dt = to_dev(g, t)
+        out = net.forward(dg, dt).cpu().numpy().astype(np.float64)
+    want, _ = M.forward(p, M.encode(g, t))
+    scale = np.abs(want).max()
+    assert np.abs(out - want).max() <= 1e-2 * scale, np.abs(out - want).max() / scale
+    assert rel(out, want) < 2e-3
+
+
+@pytest.mark.parametrize("n", [32, 1000, 4096])
+def test_gradients_match_reference(jt, n):
+    p = M.random_params(5, scale=0.7)
+    g, t, cls, size = sample(n, n)
+    with jt.MLP(4096) as net:
+        net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
+        dg, dt, lab = to_dev(g, t, cls, size)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        net.train_step(dg, dt, lab, lr=0.0, loss=loss)
+        _, grads = net.get_params(grads=True)
+        grads = M.unflatten(grads.cpu().numpy().astype(np.float64))
+        got_loss = float(loss.item())
+    want_loss, want, _ = M.loss_and_grads(p, g, t, cls, size)
+    assert abs(got_loss - want_loss) <= 1e-3 * abs(want_loss)
+    for k in M.ORDER:
+        assert rel(grads[k], want[k]) < 2e-2, (k, rel(grads[k], want[k]))
+
+
+def test_adam_step_matches_reference(jt):
+    p = M.random_params(6)
+    g, t, cls, size = sample(2048, 4)
+    lr = 1e-3
+    with jt.MLP(4096) as net:
+        net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
+        dg, dt, lab = to_dev(g, t, cls, size)
+        net.train_step(dg, dt, lab, lr=lr)
+        after, grads = net.get_params(grads=True)
+        after = M.unflatten(after.cpu().numpy().astype(np.float64))
+    _, want_g, _ = M.loss_and_grads(p, g, t, cls, size)
+    zero = {k: np.zeros_like(v) for k, v in p.items()}
+    want, _, _ = M.adam(p, want_g, zero, zero, step=1, lr=lr)
+    for k in M.ORDER:
+        step_got, step_want = p[k] - after[k], p[k] - want[k]
+        assert np.all(np.abs(step_got) <= lr * (1 + 1e-3) + 1e-7)
+        sure = np.abs(want_g[k]) > 0.05 * np.abs(want_g[k]).max()
+        assert np.allclose(step_got[sure], step_want[sure], rtol=0.05, atol=2e-6), k
+
+
+def test_training_reduces_loss_on_s28_labels(jt):
+    """Exact S_{2,8} classifications (from the HIP classifier) as labels: a
+    few hundred Adam steps cut the loss markedly (the network learns)."""
+    rng = np.random.default_rng(12)
+    gs = rng.integers(0, 1 << 24, size=1 << 17, dtype=np.uint64)
+    dg = torch.from_numpy(gs.view(np.int64)).cuda()
+    rec = jt.classify(dg, 2, 8, 16, 20, 1)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    with jt.MLP(4096) as net:
+        net.init(7)
+        losses = []
+        for step in range(300):
+            lo = (step * 4096) % (1 << 17)
+            net.train_step(dg[lo:lo + 4096], 2, rec[lo:lo + 4096], lr=1e-3, loss=loss)
+            losses.append(float(loss.item()))
+    first, last = np.mean(losses[:10]), np.mean(losses[-10:])
+    assert last < 0.5 * first, (first, last)
