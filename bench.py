@@ -11,8 +11,10 @@ After timing, each path's records are hashed per 2^20 slice and compared
 with the oracle's digests (tests/golden/s28_digests.json), so a rate counts
 only if it is bit-exact.
 
-Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this
-build measures one GPU.
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: the
+benchmark measures one GPU.  The roofline's `traffic` comes from the
+committed counter summary under profiles/ while the kernel sources are the
+ones it was taken on, else null.
 """
 import argparse
 import hashlib
@@ -60,6 +62,33 @@ def stage_ops(gold):
     }
 
 
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "batched_pipeline_s28_g16_r20_counters.md")
+KERNEL_SOURCES = ("jatam_batched.hip", "jatam_assembly.hpp", "jatam_device.hpp",
+                  "jatam_internal.hpp")
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (copy-calibrated), or None once the kernel sources differ from
+    the ones the counters were taken on."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2205_15311_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    digest = h.hexdigest()[:16]
+    try:
+        with open(COUNTER_PROFILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "traffic" and parts[1] == kernel \
+                and parts[3] == "sources":
+            return int(parts[2]) if parts[4] == digest else None
+    return None
+
+
 def cpu_baseline(threads):
     """The oracle, as it stands, on a strided 1/16 sample of S_{2,8}."""
     import numpy as np
@@ -84,7 +113,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = all usable cores, at most 16)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run 4 device copies of 256 MiB (to scale HBM counters)")
+                    help="only run 4 blits and 4 elementwise copies of 256 MiB "
+                         "(to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -100,12 +130,17 @@ def main():
         sys.exit(1)
     jt.lib()
     if args.copy_calibration:
+        # a blit (copy_) and an elementwise kernel (neg), each reading and
+        # writing 256 MiB per launch
         src = torch.ones(TOTAL * 4, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(4):
             dst.copy_(src)
+        for _ in range(4):
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 4}))
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 4,
+                          "kernels": ["copy_", "neg"]}))
         return
     with open(os.path.join(ROOT, "tests", "golden", "s28_digests.json")) as f:
         gold = json.load(f)
@@ -217,7 +252,7 @@ def main():
         },
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": None, "kernel": dominant,
+                     "traffic": profiled_traffic(dominant), "kernel": dominant,
                      "ops_per_launch": ops[dominant], "mean_launch_ms": dom_s * 1e3},
         "cpu_baseline": None,
     }
