@@ -77,6 +77,7 @@ enum {
     JATAM_E_INVALID_ARG = -1, /* argument outside the limits above             */
     JATAM_E_UNSUPPORTED = -2, /* valid model, not built for this grid size     */
     JATAM_E_HIP = -3,         /* a HIP launch or runtime call failed           */
+    JATAM_E_MISMATCH = -4,    /* autotuning: a candidate's records differed    */
 };
 
 /*
@@ -160,11 +161,71 @@ int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, 
                                uint64_t* tally, void* stream);
 
 /*
+ * Mixed items taken in the order of a queue: position p of the queue holds
+ * item order[p] (device, n x uint32, a permutation of 0..n-1; an entry >= n
+ * is skipped).  Records stay indexed by item: out[i] is item i's record,
+ * whatever the order, which only decides which wave takes which item (a
+ * queue sorted by predicted cost, for instance).  Other arguments as for
+ * jatam_batch_classify_items.
+ */
+int jatam_batch_classify_items_ordered(jatam_batch_t* batch, const jatam_item_t* items,
+                                       const uint32_t* order, int64_t n, int c, int runs,
+                                       uint64_t seed, jatam_result_t* out, uint64_t* tally,
+                                       void* stream);
+
+/*
  * Tuning of the first-run stage: a wave refills its idle lanes (screening
  * new genotypes and starting their first runs) once at least idle_lanes of
- * its 64 lanes are idle (1..64; default 24).  Records never depend on it.
+ * its 64 lanes are idle (1..64; default 24).  Sets both grid classes.
+ * Records never depend on it.
  */
 int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
+
+/*
+ * Launch parameters of the pipeline for one grid class (G <= 16 or
+ * 16 < G <= 32).  None of them changes a record.
+ *   refill        first runs: a wave refills once this many of its 64 lanes
+ *                 are idle, 1..64 (default 24)
+ *   first_waves   persistent one-wave workgroups per CU of the first-run
+ *                 stage, >= 1; capped at what fits in a CU (default: that)
+ *   repeat_waves  the same for the repeat stage
+ *   wide_layout   G <= 16 class only: 1 classifies these genotypes with the
+ *                 32 x 32 LDS layout (and the other class's parameters)
+ *                 instead of the 16 x 16 one (default 0)
+ */
+typedef struct {
+    int refill;
+    int first_waves;
+    int repeat_waves;
+    int wide_layout;
+} jatam_tuning_t;
+
+/* The parameters used for grid_limit's class (8 <= grid_limit <= 32). */
+int jatam_batch_get_tuning(const jatam_batch_t* batch, int grid_limit, jatam_tuning_t* tuning);
+int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tuning_t* tuning);
+
+/*
+ * Autotuner: picks the parameters of grid_limit's class by timing the
+ * pipeline on a lexicographic sample [first, first + n) (arguments as for
+ * jatam_batch_classify_range, 1 <= n <= the workspace's max_n).  Starting
+ * from the current parameters it tries, one field at a time, refill in
+ * {8, 16, 24, 32, 48}, first_waves and repeat_waves at and below the
+ * residency limit, and (G <= 16) both layouts, keeping a value when the
+ * median of three timed calls improves.  Every candidate's records are
+ * compared with the starting configuration's, bit for bit: a difference
+ * stops the search with JATAM_E_MISMATCH.  The best parameters found are
+ * set on the workspace and written to *best (if not NULL).
+ *   scratch  device, 2n records, caller-owned, overwritten
+ * Synchronises the stream; allocates nothing on the device.
+ */
+int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t, int c,
+                         int grid_limit, int runs, uint64_t seed, jatam_result_t* scratch,
+                         jatam_tuning_t* best, void* stream);
+
+/* Entry i of the last autotune's log (the configuration and its median ms);
+ * returns the number of entries (i < 0: only that). */
+int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* tuning,
+                             double* ms);
 
 /*
  * Timing hook of the pipeline, for measurement.  While enabled, every call on
@@ -300,6 +361,36 @@ int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* ml
                            int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
                            int32_t generation, int oversample, uint64_t* next_pop,
                            int32_t* next_fit, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Shape histogram (§3.4: the paper histograms the shape hashes of every
+ * slice, on the host, while the next slice is classified).  Kept on the
+ * device here.
+ * ------------------------------------------------------------------------ */
+
+/* One entry: a deterministic shape (its D4 hash and size) and how many DET
+ * records have it.  size == 0 marks an empty entry. */
+typedef struct {
+    uint32_t hash;
+    int32_t  size;
+    uint64_t count;
+} jatam_shape_count_t;   /* 16 bytes */
+
+/*
+ * Adds the DET records of recs[0..n) to a shape histogram.
+ *   recs      device, n records (any call's output; non-DET records ignored)
+ *   table     device, capacity entries, open addressing keyed by
+ *             (hash, size); zero it before its first use; counts are ADDED,
+ *             so one table can collect many slices.  Entry order is not
+ *             meaningful.
+ *   capacity  a power of two in [64, 2^24]
+ *   overflow  NULL, or device uint64[1] to which the number of DET records
+ *             that found no free entry is added (0 unless the table is full)
+ * JATAM_E_INVALID_ARG for a bad capacity or n < 0.  Calls adding to one
+ * table must be serialised (same stream).
+ */
+int jatam_shape_histogram(const jatam_result_t* recs, int64_t n, jatam_shape_count_t* table,
+                          int64_t capacity, uint64_t* overflow, void* stream);
 
 /* Static description of an error code. */
 const char* jatam_strerror(int code);

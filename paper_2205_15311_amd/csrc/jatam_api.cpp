@@ -3,6 +3,7 @@
 // allocates (its workspace); no exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -11,12 +12,14 @@
 struct jatam_batch {
     int device;
     int64_t max_n;
-    int blocks[2][2];              // persistent grid per grid class and tile bound
+    int cus;                       // compute units of the device
+    int occ[2][2][2];              // resident blocks per CU [class][tile bound][stage]
+    jatam_tuning_t tune[2];        // launch parameters per grid class
+    std::vector<std::pair<jatam_tuning_t, double>> tune_log;   // last autotune
     jatam::DeviceWorkspace ws;
-    void* allocations[16];
+    void* allocations[20];
     int nalloc;
     // timing hook: one set of stage events per call made while enabled
-    int refill;                    // idle lanes that trigger a first-run refill
     bool timing;
     std::vector<hipEvent_t> marks;        // 2 * kStages per recorded call
     std::vector<uint8_t> launched;        // kStages per recorded call
@@ -55,11 +58,21 @@ int make_params(int t, int c, int grid, int runs, uint64_t seed, jatam::Params* 
     return JATAM_OK;
 }
 
+// Candidate values of one tuning field, around the residency limit `occ`.
+std::vector<int> wave_choices(int occ)
+{
+    std::vector<int> v;
+    for (int w : {occ, occ - 1, occ - 2, (occ + 1) / 2})
+        if (w >= 1 && std::find(v.begin(), v.end(), w) == v.end())
+            v.push_back(w);
+    return v;
+}
+
 }  // namespace
 
 extern "C" {
 
-int jatam_abi_version(void) { return 2; }
+int jatam_abi_version(void) { return 3; }
 
 const char* jatam_strerror(int code)
 {
@@ -68,6 +81,7 @@ const char* jatam_strerror(int code)
     case JATAM_E_INVALID_ARG: return "invalid argument";
     case JATAM_E_UNSUPPORTED: return "unsupported configuration";
     case JATAM_E_HIP: return "HIP runtime error";
+    case JATAM_E_MISMATCH: return "a launch configuration changed the records";
     default: return "unknown error";
     }
 }
@@ -142,16 +156,28 @@ static int next_marks(jatam_batch_t* b, hipEvent_t** marks, uint8_t** launched)
     return JATAM_OK;
 }
 
-static int launch_timed(jatam_batch_t* b, const jatam::BatchArgs& a, const bool classes[2],
-                        int max_t, hipStream_t stream)
+// Launches the pipeline.  grid_limit: the uniform G of the call, or 0 for
+// mixed items (both grid classes).
+static int launch_timed(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
+                        hipStream_t stream)
 {
     hipEvent_t* marks;
     uint8_t* launched;
     const int rc = next_marks(b, &marks, &launched);
     if (rc != JATAM_OK)
         return rc;
-    return jatam::launch_batched(a, classes, b->blocks, max_t <= 2 ? 2 : 4, stream, marks,
-                                 launched);
+    const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
+    a.narrow_max = b->tune[0].wide_layout ? 0 : 16;
+    const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
+                             grid_limit == 0 || grid_limit > a.narrow_max};
+    jatam::StageLaunch launch[2];
+    for (int k = 0; k < 2; ++k) {
+        const jatam_tuning_t& t = b->tune[k];
+        const int fw = t.first_waves < b->occ[k][ti][0] ? t.first_waves : b->occ[k][ti][0];
+        const int rw = t.repeat_waves < b->occ[k][ti][1] ? t.repeat_waves : b->occ[k][ti][1];
+        launch[k] = jatam::StageLaunch{t.refill, fw * b->cus, rw * b->cus};
+    }
+    return jatam::launch_batched(a, classes, launch, tm, stream, marks, launched);
 }
 
 static bool batch_alloc(jatam_batch_t* b, size_t bytes, void** out)
@@ -175,18 +201,29 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->max_n = max_n;
     b->nalloc = 0;
     b->timing = false;
-    b->refill = 24;
+    for (int k = 0; k < 2; ++k)
+        b->tune[k] = jatam_tuning_t{24, 64, 64, 0};
     hipDeviceProp_t prop;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
         delete b;
         return JATAM_E_HIP;
     }
-    jatam::batch_persistent_blocks(prop.multiProcessorCount, b->blocks);
+    b->cus = prop.multiProcessorCount;
+    jatam::batch_occupancy(b->occ);
+    // first-run grids set the number of staging segments
     int max_blocks = 1;
     for (int k = 0; k < 2; ++k)
         for (int i = 0; i < 2; ++i)
-            max_blocks = b->blocks[k][i] > max_blocks ? b->blocks[k][i] : max_blocks;
+            max_blocks = b->occ[k][i][0] * b->cus > max_blocks ? b->occ[k][i][0] * b->cus
+                                                                : max_blocks;
+    // the size scan covers kSizeBuckets * max_blocks histogram entries in at
+    // most kMaxScanBlocks blocks
+    if ((size_t)jatam::kSizeBuckets * max_blocks >
+        (size_t)jatam::kScanBlock * jatam::kMaxScanBlocks) {
+        delete b;
+        return JATAM_E_UNSUPPORTED;
+    }
     const size_t n = (size_t)max_n;
     const size_t staging = n + 64 * ((size_t)max_blocks + 1);
     jatam::DeviceWorkspace& ws = b->ws;
@@ -197,6 +234,8 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
         ok = batch_alloc(b, (size_t)max_blocks * sizeof(uint32_t), (void**)&ws.seg_count[k]) &&
              batch_alloc(b, (size_t)jatam::kSizeBuckets * max_blocks * sizeof(uint32_t),
                          (void**)&ws.seg_hist[k]) &&
+             batch_alloc(b, (size_t)jatam::kMaxScanBlocks * sizeof(uint32_t),
+                         (void**)&ws.scan_sums[k]) &&
              batch_alloc(b, staging * sizeof(uint32_t), (void**)&ws.cand_idx[k]) &&
              batch_alloc(b, staging * sizeof(uint16_t), (void**)&ws.cand_size[k]) &&
              batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.sorted[k]);
@@ -252,7 +291,9 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.runs = p.runs;
     a.key0 = p.key0;
     a.key1 = p.key1;
-    a.refill = b->refill;
+    a.order = nullptr;
+    a.narrow_max = 16;
+    a.refill = 24;
     a.seg_cap = 0;
     a.out = out;
     a.tally = reinterpret_cast<unsigned long long*>(tally);
@@ -274,8 +315,7 @@ int jatam_batch_classify(jatam_batch_t* batch, const uint64_t* genotypes, int64_
         return JATAM_E_INVALID_ARG;
     jatam::BatchArgs a = batch_args(batch, p, n, out, tally);
     a.genomes = genotypes;
-    const bool classes[2] = {grid_limit <= 16, grid_limit > 16};
-    return launch_timed(batch, a, classes, t, (hipStream_t)stream);
+    return launch_timed(batch, a, grid_limit, t, (hipStream_t)stream);
 }
 
 int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, int t, int c,
@@ -295,13 +335,21 @@ int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, 
     }
     jatam::BatchArgs a = batch_args(batch, p, n, out, tally);
     a.first = first;
-    const bool classes[2] = {grid_limit <= 16, grid_limit > 16};
-    return launch_timed(batch, a, classes, t, (hipStream_t)stream);
+    return launch_timed(batch, a, grid_limit, t, (hipStream_t)stream);
 }
 
 int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, int64_t n,
                                int c, int runs, uint64_t seed, jatam_result_t* out,
                                uint64_t* tally, void* stream)
+{
+    return jatam_batch_classify_items_ordered(batch, items, nullptr, n, c, runs, seed, out, tally,
+                                              stream);
+}
+
+int jatam_batch_classify_items_ordered(jatam_batch_t* batch, const jatam_item_t* items,
+                                       const uint32_t* order, int64_t n, int c, int runs,
+                                       uint64_t seed, jatam_result_t* out, uint64_t* tally,
+                                       void* stream)
 {
     jatam::Params p;
     // t and grid are per item; validate the shared arguments with placeholders
@@ -314,16 +362,151 @@ int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, 
         return JATAM_E_INVALID_ARG;
     jatam::BatchArgs a = batch_args(batch, p, n, out, tally);
     a.items = items;
-    const bool classes[2] = {true, true};
-    return launch_timed(batch, a, classes, 4, (hipStream_t)stream);
+    a.order = order;
+    return launch_timed(batch, a, 0, 4, (hipStream_t)stream);
 }
 
 int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes)
 {
     if (batch == nullptr || idle_lanes < 1 || idle_lanes > 64)
         return JATAM_E_INVALID_ARG;
-    batch->refill = idle_lanes;
+    batch->tune[0].refill = idle_lanes;
+    batch->tune[1].refill = idle_lanes;
     return JATAM_OK;
+}
+
+int jatam_batch_get_tuning(const jatam_batch_t* batch, int grid_limit, jatam_tuning_t* tuning)
+{
+    if (batch == nullptr || tuning == nullptr || grid_limit < 8 || grid_limit > 32)
+        return JATAM_E_INVALID_ARG;
+    *tuning = batch->tune[grid_limit <= 16 ? 0 : 1];
+    return JATAM_OK;
+}
+
+int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tuning_t* tuning)
+{
+    if (batch == nullptr || tuning == nullptr || grid_limit < 8 || grid_limit > 32 ||
+        tuning->refill < 1 || tuning->refill > 64 || tuning->first_waves < 1 ||
+        tuning->repeat_waves < 1 || tuning->wide_layout < 0 || tuning->wide_layout > 1 ||
+        (grid_limit > 16 && tuning->wide_layout != 0))
+        return JATAM_E_INVALID_ARG;
+    batch->tune[grid_limit <= 16 ? 0 : 1] = *tuning;
+    return JATAM_OK;
+}
+
+int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t, int c,
+                         int grid_limit, int runs, uint64_t seed, jatam_result_t* scratch,
+                         jatam_tuning_t* best, void* stream)
+{
+    if (batch == nullptr || scratch == nullptr || n < 1 || n > batch->max_n)
+        return JATAM_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int k = grid_limit <= 16 ? 0 : 1;
+    const int ti = t <= 2 ? 0 : 1;
+    jatam_result_t* ref = scratch;
+    jatam_result_t* cand = scratch + n;
+    uint32_t* flag = batch->ws.counters + jatam::kCntDiff;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return JATAM_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return JATAM_E_HIP;
+    }
+    batch->tune_log.clear();
+    int rc = JATAM_OK;
+    // median of three timed calls after one warm-up; records into `dst`
+    auto measure = [&](jatam_result_t* dst, double* ms) -> int {
+        float v[3];
+        for (int r = 0; r < 4; ++r) {
+            if (r > 0 && hipEventRecord(e0, s) != hipSuccess)
+                return JATAM_E_HIP;
+            const int q = jatam_batch_classify_range(batch, first, n, t, c, grid_limit, runs,
+                                                     seed, dst, nullptr, stream);
+            if (q != JATAM_OK)
+                return q;
+            if (r > 0) {
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&v[r - 1], e0, e1) != hipSuccess)
+                    return JATAM_E_HIP;
+            }
+        }
+        std::sort(v, v + 3);
+        *ms = v[1];
+        return JATAM_OK;
+    };
+    // the records of a candidate must equal the reference's, bit for bit
+    auto same = [&](bool* ok) -> int {
+        uint32_t h = 0;
+        if (hipMemsetAsync(flag, 0, sizeof(uint32_t), s) != hipSuccess ||
+            jatam::launch_records_differ(ref, cand, (uint64_t)n, flag, s) != JATAM_OK ||
+            hipMemcpyAsync(&h, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return JATAM_E_HIP;
+        *ok = h == 0;
+        return JATAM_OK;
+    };
+    jatam_tuning_t cur = batch->tune[k];
+    double cur_ms = 0;
+    if ((rc = measure(ref, &cur_ms)) != JATAM_OK)
+        goto done;
+    batch->tune_log.push_back({cur, cur_ms});
+    // one field at a time, keeping the best value of each
+    for (int field = 0; field < 4 && rc == JATAM_OK; ++field) {
+        std::vector<int> choices;
+        if (field == 0)
+            choices = {8, 16, 24, 32, 48};
+        else if (field == 1)
+            choices = wave_choices(batch->occ[k][ti][0]);
+        else if (field == 2)
+            choices = wave_choices(batch->occ[k][ti][1]);
+        else if (k == 0)
+            choices = {0, 1};
+        for (int v : choices) {
+            jatam_tuning_t trial = cur;
+            int* slot = field == 0 ? &trial.refill : field == 1 ? &trial.first_waves
+                      : field == 2 ? &trial.repeat_waves : &trial.wide_layout;
+            if (*slot == v || (field == 1 && v >= batch->occ[k][ti][0] && cur.first_waves >= v) ||
+                (field == 2 && v >= batch->occ[k][ti][1] && cur.repeat_waves >= v))
+                continue;
+            *slot = v;
+            batch->tune[k] = trial;
+            double ms = 0;
+            bool ok = false;
+            if ((rc = measure(cand, &ms)) != JATAM_OK || (rc = same(&ok)) != JATAM_OK)
+                break;
+            if (!ok) {
+                rc = JATAM_E_MISMATCH;
+                break;
+            }
+            batch->tune_log.push_back({trial, ms});
+            if (ms < cur_ms) {
+                cur = trial;
+                cur_ms = ms;
+            }
+        }
+    }
+done:
+    batch->tune[k] = cur;
+    if (best != nullptr)
+        *best = cur;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* tuning, double* ms)
+{
+    if (batch == nullptr)
+        return JATAM_E_INVALID_ARG;
+    const int count = (int)batch->tune_log.size();
+    if (i < 0)
+        return count;
+    if (i >= count || tuning == nullptr || ms == nullptr)
+        return JATAM_E_INVALID_ARG;
+    *tuning = batch->tune_log[(size_t)i].first;
+    *ms = batch->tune_log[(size_t)i].second;
+    return count;
 }
 
 int jatam_batch_set_timing(jatam_batch_t* batch, int enable)
@@ -743,3 +926,24 @@ int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* ml
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Shape histogram.
+// ---------------------------------------------------------------------------
+extern "C" int jatam_shape_histogram(const jatam_result_t* recs, int64_t n,
+                                     jatam_shape_count_t* table, int64_t capacity,
+                                     uint64_t* overflow, void* stream)
+{
+    if (n < 0 || capacity < 64 || capacity > (1 << 24) || (capacity & (capacity - 1)) != 0 ||
+        table == nullptr || (n > 0 && recs == nullptr))
+        return JATAM_E_INVALID_ARG;
+    int log2cap = 0;
+    while ((int64_t(1) << log2cap) < capacity)
+        ++log2cap;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return JATAM_E_HIP;
+    return jatam::launch_shape_hist(recs, (uint64_t)n, table, log2cap, overflow, cus,
+                                    (hipStream_t)stream);
+}

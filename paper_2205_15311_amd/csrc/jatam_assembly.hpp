@@ -152,10 +152,27 @@ __device__ __forceinline__ int update_site(const Model<TM>& m, LaneGrid<W, B>& g
     return unbound ? kEvUnbound : ambiguous ? kEvAmbig : kEvNone;
 }
 
-// Philox block cache of a run: the 4 words of counter block `block`.
+// Philox block cache of a run: the 4 words of counter block `block`.  Kept
+// as four scalars, never an array: an array picked by a run-time index ends
+// up in scratch memory, one memory round trip per step.
 struct DrawCache {
     uint32_t block;
-    Words4 words;
+    uint32_t w0, w1, w2, w3;
+
+    __device__ __forceinline__ void fill(const Words4& v)
+    {
+        w0 = v.w[0];
+        w1 = v.w[1];
+        w2 = v.w[2];
+        w3 = v.w[3];
+    }
+    // word k (0..3) by two register selects
+    __device__ __forceinline__ uint32_t word(uint32_t k) const
+    {
+        const uint32_t lo = (k & 1u) ? w1 : w0;
+        const uint32_t hi = (k & 1u) ? w3 : w2;
+        return (k & 2u) ? hi : lo;
+    }
 };
 
 // Starts a run: clears what the previous run touched, places the seed
@@ -207,15 +224,10 @@ __device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, R
         st.choice = true;
         const uint32_t blk = (uint32_t)st.steps >> 2;
         if (blk != dc.block) {
-            dc.words = philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1);
+            dc.fill(philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
             dc.block = blk;
         }
-        const int k = st.steps & 3;
-        uint32_t u = dc.words.w[0];
-        u = k == 1 ? dc.words.w[1] : u;
-        u = k == 2 ? dc.words.w[2] : u;
-        u = k == 3 ? dc.words.w[3] : u;
-        j = __umulhi(u, st.nf);
+        j = __umulhi(dc.word((uint32_t)st.steps & 3u), st.nf);
     }
     // the j-th frontier site in row-major order
     int w = 0;
@@ -443,6 +455,125 @@ __device__ __forceinline__ bool shape_bitmap8(LaneGrid<W, B>& g, int G, uint64_t
         m |= (uint64_t)((g.row(bx.ymin + y) >> bx.xmin) & 0xFFu) << (8 * y);
     return true;
 }
+
+// Width and height of an anchored 8 x 8 bitmap (not empty).
+__device__ __forceinline__ void bitmap8_dims(uint64_t m, int& w, int& h)
+{
+    uint32_t x = (uint32_t)m | (uint32_t)(m >> 32);
+    x |= x >> 16;
+    x |= x >> 8;
+    w = 32 - __builtin_clz(x & 0xFFu);
+    h = (63 - __builtin_clzll(m)) / 8 + 1;
+}
+
+// The cropped shape as an anchored 8 x 8 bitmap for W = 16, from the 8 OCC
+// words at once: row masks and the column union give the bounding box; each
+// word (two rows) is shifted to xmin and packed to two bytes; the 8-row
+// window at ymin is cut from the 16 packed rows.  False if the box exceeds
+// 8 x 8.
+template <int B>
+__device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& m)
+{
+    uint32_t o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        o[k] = g.occ(k);
+    uint32_t rows = 0, cols = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        rows |= (uint32_t)((o[k] & 0xFFFFu) != 0) << (2 * k);
+        rows |= (uint32_t)((o[k] >> 16) != 0) << (2 * k + 1);
+        cols |= o[k];
+    }
+    cols = (cols | (cols >> 16)) & 0xFFFFu;
+    const int ymin = __builtin_ctz(rows), ymax = 31 - __builtin_clz(rows);
+    const int xmin = __builtin_ctz(cols), xmax = 31 - __builtin_clz(cols);
+    if (xmax - xmin >= 8 || ymax - ymin >= 8)
+        return false;
+    uint32_t r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t a = (o[2 * q] >> xmin) & 0x00FF00FFu;
+        const uint32_t b = (o[2 * q + 1] >> xmin) & 0x00FF00FFu;
+        r[q] = ((a | (a >> 8)) & 0xFFFFu) | (((b | (b >> 8)) & 0xFFFFu) << 16);
+    }
+    // bytes ymin .. ymin+7 of r[0..3] (rows past 15 are empty)
+    const int q = ymin >> 2, sh = 8 * (ymin & 3);
+    const uint32_t a0 = q == 0 ? r[0] : q == 1 ? r[1] : q == 2 ? r[2] : r[3];
+    const uint32_t a1 = q == 0 ? r[1] : q == 1 ? r[2] : q == 2 ? r[3] : 0u;
+    const uint32_t a2 = q == 0 ? r[2] : q == 1 ? r[3] : 0u;
+    const uint32_t lo = (uint32_t)((((uint64_t)a1 << 32) | a0) >> sh);
+    const uint32_t hi = (uint32_t)((((uint64_t)a2 << 32) | a1) >> sh);
+    m = ((uint64_t)hi << 32) | lo;
+    return true;
+}
+
+// The cropped shape as an anchored 8 x 8 bitmap, whatever W.
+template <int W, int B>
+__device__ __forceinline__ bool shape_key8(LaneGrid<W, B>& g, int G, uint64_t& m)
+{
+    if constexpr (W == 16) {
+        return shape_bitmap8_w16(g, m);
+    } else {
+        int w, h;
+        return shape_bitmap8(g, G, m, w, h);
+    }
+}
+
+// D4 hash of a shape given as an anchored 8 x 8 bitmap, by one lane.
+__device__ __forceinline__ uint32_t bitmap8_shape_hash(uint64_t m)
+{
+    int w, h;
+    bitmap8_dims(m, w, h);
+    uint32_t hs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        hs[k] = bitmap_hash8(image8(m, w, h, k));
+    return combine_orientations(hs);
+}
+
+// Per-wave cache of D4 hashes in LDS, keyed by the exact anchored 8 x 8
+// bitmap of a shape (which determines the shape, so a hit returns exactly
+// the hash the shape has).  N entries {bitmap lo, bitmap hi, hash, 0},
+// direct mapped; an all-zero key marks an empty entry (no shape is empty).
+// Lanes read it freely; entries are written one lane at a time.  For
+// workgroups of one wave (insert synchronises the workgroup).
+template <int N>
+struct ShapeCache {
+    static_assert((N & (N - 1)) == 0, "N must be a power of two");
+    uint4* e;
+
+    __device__ __forceinline__ static uint32_t slot(uint64_t m)
+    {
+        const uint32_t x = (uint32_t)m * 0x9E3779B1u ^ (uint32_t)(m >> 32) * 0x85EBCA77u;
+        return (x ^ (x >> 15)) & (N - 1);
+    }
+    __device__ __forceinline__ void clear(int lane)
+    {
+        for (int i = lane; i < N; i += 64)
+            e[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __device__ __forceinline__ bool lookup(uint64_t m, uint32_t& hash) const
+    {
+        const uint4 v = e[slot(m)];
+        hash = v.z;
+        return v.x == (uint32_t)m && v.y == (uint32_t)(m >> 32);
+    }
+    // Called by the whole wave: every lane with `want` stores its entry, in
+    // lane order (a later lane with the same slot overwrites), then the
+    // wave's LDS writes are complete before any later lookup.
+    __device__ __forceinline__ void insert(bool want, uint64_t m, uint32_t hash, int lane)
+    {
+        uint64_t pending = __ballot(want);
+        if (pending == 0)
+            return;
+        for (; pending != 0; pending &= pending - 1) {
+            if (lane == __builtin_ctzll(pending))
+                e[slot(m)] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), hash, 0u);
+        }
+        __syncthreads();
+    }
+};
 
 // D4-invariant hash of the shape held in OCC, computed by one lane.
 template <int W, int B>

@@ -69,7 +69,11 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint32_t i)
     return g;
 }
 
-__device__ __forceinline__ int grid_class(int grid) { return grid <= 16 ? 0 : 1; }
+// Grid class of a genotype: 0 = the 16 x 16 layout, 1 = the 32 x 32 layout.
+__device__ __forceinline__ int grid_class(const BatchArgs& a, int grid)
+{
+    return grid <= a.narrow_max ? 0 : 1;
+}
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -94,15 +98,36 @@ struct WaveTally {
     }
 };
 
-// A monomer and a domino have one shape each up to D4: their hashes are
-// computed once per workspace (small_hash_kernel) by the general function.
+// LDS entries of the per-wave shape-hash cache.
+constexpr int kShapeCache = 32;
+using WaveShapeCache = ShapeCache<kShapeCache>;
+
+// D4 hash of the DET shape in a lane's OCC, for lanes with `want` (called by
+// the whole wave).  A monomer and a domino have one shape each up to D4:
+// their hashes are computed once per workspace (small_hash_kernel).  Shapes
+// that fit 8 x 8 go through the wave's cache; a miss hashes the bitmap and
+// fills the cache.
 template <int W>
-__device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs& a, int size,
-                                             int grid)
+__device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs& a,
+                                             WaveShapeCache& cache, bool want, int size, int grid)
 {
-    if (size <= 2)
-        return a.ws.small_hash[size - 1];
-    return shape_hash(g, grid);
+    uint32_t h = 0;
+    bool miss = false;
+    uint64_t key = 0;
+    if (want) {
+        if (size <= 2) {
+            h = a.ws.small_hash[size - 1];
+        } else if (shape_key8(g, grid, key)) {
+            if (!cache.lookup(key, h)) {
+                h = bitmap8_shape_hash(key);
+                miss = true;
+            }
+        } else {
+            h = shape_hash(g, grid);
+        }
+    }
+    cache.insert(miss, key, h, lane_id());
+    return h;
 }
 
 // ---------------------------------------------------------------------------
@@ -116,8 +141,12 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
     using Geo = Geometry<W>;
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t ring[kRing];
+    __shared__ uint4 cache_mem[kShapeCache];
     LaneGrid<W, 64> g{smem + threadIdx.x};
     g.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
     RunState st{0, 0, 0, 0, 0, false};
     DrawCache dc;
     dc.block = 0xFFFFFFFFu;
@@ -144,16 +173,22 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
         if (nidle >= (uint32_t)a.refill || nidle == 64) {
             while (queued < nidle && next_chunk < nchunks) {
                 // screen one chunk of the input (§3.2: what the seed decides)
-                const uint32_t i = next_chunk * 64 + (uint32_t)lane_id();
+                const uint32_t pos = next_chunk * 64 + (uint32_t)lane_id();
+                uint32_t i = pos;
+                bool in_range = pos < (uint64_t)a.n;
+                if (in_range && a.order != nullptr) {
+                    i = a.order[pos];
+                    in_range = i < (uint64_t)a.n;   // an entry out of range is skipped
+                }
                 bool done = false, keep = false;
                 int cls = 0;
-                if (i < (uint64_t)a.n) {
+                if (in_range) {
                     const Geno s = fetch_geno(a, i);
                     if (!s.valid) {
                         // exactly one launched pass reports an invalid item
-                        if (grid_class(s.grid) == klass)
+                        if (grid_class(a, s.grid) == klass)
                             a.out[i] = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
-                    } else if (grid_class(s.grid) == klass) {
+                    } else if (grid_class(a, s.grid) == klass) {
                         const Model<TM> sm = build_model<TM>(s.genome, s.t, a.bits, a.c);
                         const uint32_t seed = seed_tile(sm);
                         bool ambiguous = false, bonds = false;
@@ -210,10 +245,10 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
                           (uint32_t)(gd.rng_id >> 32));
         // -- lanes whose first run is over ----------------------------------
         const bool finish = busy && run_over(ev, st, gd.grid);
-        bool done = false, candidate = false;
+        bool done = false, candidate = false, det = false;
         int cls = 0;
+        jatam_result_t rec{0, 0, 0u, 0};
         if (finish) {
-            jatam_result_t rec;
             done = true;
             if (ev == kEvCorrupt) {
                 rec = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
@@ -224,12 +259,16 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
             } else if (!st.choice || a.runs == 1) {
                 // no random word was drawn: every run would be this run
                 cls = JATAM_DET;
-                rec = jatam_result_t{JATAM_DET, st.size, det_hash(g, a, st.size, gd.grid),
-                                     st.steps};
+                det = true;
+                rec = jatam_result_t{JATAM_DET, st.size, 0u, st.steps};
             } else {
                 done = false;
                 candidate = true;
             }
+        }
+        if (__ballot(det) != 0)
+            rec.hash = det_hash(g, a, cache, det, st.size, gd.grid);
+        if (finish) {
             if (done)
                 a.out[idx] = rec;
             busy = false;
@@ -275,34 +314,70 @@ __global__ __launch_bounds__(256) void sort_hist_kernel(BatchArgs a, int klass)
         a.ws.seg_hist[klass][threadIdx.x * nseg + seg] = hist[threadIdx.x];
 }
 
-// Exclusive scan of the bucket-major histogram, in place; the total is the
-// candidate count.
-__global__ __launch_bounds__(1024) void sort_scan_kernel(BatchArgs a, int klass, uint32_t nseg)
+// Exclusive scan of the bucket-major histogram in three coalesced passes:
+// each block scans kScanBlock entries in place and writes its total; one
+// block scans the totals (and stores the candidate count); the scatter adds
+// the block offsets.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
 {
-    __shared__ uint32_t part[1024];
-    uint32_t* h = a.ws.seg_hist[klass];
-    const uint32_t total = kSizeBuckets * nseg;
-    const uint32_t per = (total + 1023) / 1024;
-    const uint32_t lo = threadIdx.x * per, hi = min(total, lo + per);
-    uint32_t sum = 0;
-    for (uint32_t i = lo; i < hi; ++i)
-        sum += h[i];
-    part[threadIdx.x] = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off);
+        v += lane_id() >= off ? u : 0u;
+    }
+    return v;
+}
+
+// Exclusive scan of kScanBlock values across a 1024-thread block; *total
+// receives their sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum,
+                                                         uint32_t* total)
+{
+    const uint32_t w = threadIdx.x >> 6, l = lane_id();
+    const uint32_t incl = wave_inclusive_scan(v);
+    if (l == 63)
+        wsum[w] = incl;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
+    if (w == 0) {
+        const uint32_t x = l < kScanBlock / 64 ? wsum[l] : 0u;
+        const uint32_t xi = wave_inclusive_scan(x);
+        if (l < kScanBlock / 64)
+            wsum[l] = xi - x;
+        if (l == kScanBlock / 64 - 1)
+            wsum[kScanBlock / 64] = xi;
     }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const uint32_t v = h[i];
-        h[i] = run;
-        run += v;
-    }
-    if (threadIdx.x == 1023)
-        a.ws.counters[kCntCand + klass] = part[1023];
+    __syncthreads();
+    *total = wsum[kScanBlock / 64];
+    return wsum[w] + incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void sort_scan_kernel(BatchArgs a, int klass,
+                                                               uint32_t total)
+{
+    __shared__ uint32_t wsum[kScanBlock / 64 + 1];
+    uint32_t* h = a.ws.seg_hist[klass];
+    const uint32_t i = blockIdx.x * kScanBlock + threadIdx.x;
+    const uint32_t v = i < total ? h[i] : 0u;
+    uint32_t sum;
+    const uint32_t excl = block_exclusive_scan(v, wsum, &sum);
+    if (i < total)
+        h[i] = excl;
+    if (threadIdx.x == 0)
+        a.ws.scan_sums[klass][blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanBlock) void sort_scan_sums_kernel(BatchArgs a, int klass,
+                                                                    uint32_t nblocks)
+{
+    __shared__ uint32_t wsum[kScanBlock / 64 + 1];
+    uint32_t* sums = a.ws.scan_sums[klass];
+    const uint32_t v = threadIdx.x < nblocks ? sums[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan(v, wsum, &total);
+    if (threadIdx.x < nblocks)
+        sums[threadIdx.x] = excl;
+    if (threadIdx.x == 0)
+        a.ws.counters[kCntCand + klass] = total;
 }
 
 // One block per segment: place its candidates with LDS cursors per bucket.
@@ -310,8 +385,10 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
 {
     __shared__ uint32_t cursor[kSizeBuckets];
     const uint32_t seg = blockIdx.x, nseg = gridDim.x;
-    if (threadIdx.x < kSizeBuckets)
-        cursor[threadIdx.x] = a.ws.seg_hist[klass][threadIdx.x * nseg + seg];
+    if (threadIdx.x < kSizeBuckets) {
+        const uint32_t e = threadIdx.x * nseg + seg;
+        cursor[threadIdx.x] = a.ws.seg_hist[klass][e] + a.ws.scan_sums[klass][e / kScanBlock];
+    }
     __syncthreads();
     const uint32_t n = a.ws.seg_count[klass][seg];
     const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
@@ -341,8 +418,12 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
     using Geo = Geometry<W>;
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t orient[8][64];   // per group: the 8 orientation hashes
+    __shared__ uint4 cache_mem[kShapeCache];
     LaneGrid<W, 64> g{smem + threadIdx.x};
     g.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
     RunState st{0, 0, 0, 0, 0, false};
     WaveTally tally{{0, 0, 0, 0}};
 
@@ -407,28 +488,37 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
         const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead);
         const bool det = active && cls == JATAM_DET;
         const int size0 = __shfl(st.size, lead);
-        // the group's lanes share the 8 orientation hashes of run 0's shape
+        // run 0's shape: from the wave's cache, else the group's lanes share
+        // its 8 orientation hashes
+        uint64_t key = 0;
+        bool small = false, hit = false;
+        uint32_t cached = 0;
         if (det && size0 > 2) {
-            uint64_t m8;
-            int w8, h8;
-            const bool small = shape_bitmap8(g0, gd.grid, m8, w8, h8);
-            for (int k = run; k < 8; k += R) {
+            small = shape_key8(g0, gd.grid, key);
+            hit = small && cache.lookup(key, cached);
+            if (!hit) {
                 if (small) {
-                    orient[k][grp] = bitmap_hash8(image8(m8, w8, h8, k));
+                    int w8, h8;
+                    bitmap8_dims(key, w8, h8);
+                    for (int k = run; k < 8; k += R)
+                        orient[k][grp] = bitmap_hash8(image8(key, w8, h8, k));
                 } else {
                     const ShapeBox bx = crop(g0, gd.grid);
-                    orient[k][grp] = orientation_hash(g0, bx, k);
+                    for (int k = run; k < 8; k += R)
+                        orient[k][grp] = orientation_hash(g0, bx, k);
                 }
             }
         }
         __syncthreads();
         const bool done = active && run == 0;
+        uint32_t h = 0;
         if (done) {
             jatam_result_t rec;
             if (det) {
-                uint32_t h;
                 if (size0 <= 2) {
                     h = a.ws.small_hash[size0 - 1];
+                } else if (hit) {
+                    h = cached;
                 } else {
                     uint32_t hs[8];
 #pragma unroll
@@ -445,6 +535,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             a.out[idx] = rec;
         }
         tally.add(done, cls);
+        cache.insert(done && det && small && !hit, key, h, lane);
         __syncthreads();   // orientation slots and grids reused next round
     }
     tally.flush(a.tally);
@@ -477,28 +568,57 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream)
 }
 
 template <int W, int TM>
-static int blocks_for(int cus)
+static void occupancy_of(int out[2])
 {
-    int a = 0, b = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, first_run_kernel<W, TM>, 64, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, repeat_kernel<W, TM>, 64, 0);
-    const int p = a < b ? a : b;
-    return (p > 0 ? p : 1) * cus;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[0], first_run_kernel<W, TM>, 64, 0) !=
+            hipSuccess ||
+        out[0] < 1)
+        out[0] = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[1], repeat_kernel<W, TM>, 64, 0) !=
+            hipSuccess ||
+        out[1] < 1)
+        out[1] = 1;
 }
 
-void batch_persistent_blocks(int cus, int blocks[2][2])
+void batch_occupancy(int occ[2][2][2])
 {
-    blocks[0][0] = blocks_for<16, 2>(cus);
-    blocks[0][1] = blocks_for<16, 4>(cus);
-    blocks[1][0] = blocks_for<32, 2>(cus);
-    blocks[1][1] = blocks_for<32, 4>(cus);
+    occupancy_of<16, 2>(occ[0][0]);
+    occupancy_of<16, 4>(occ[0][1]);
+    occupancy_of<32, 2>(occ[1][0]);
+    occupancy_of<32, 4>(occ[1][1]);
+}
+
+__global__ __launch_bounds__(256) void records_differ_kernel(const int4* __restrict__ x,
+                                                             const int4* __restrict__ y,
+                                                             uint64_t n, uint32_t* flag)
+{
+    bool differ = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256) {
+        const int4 u = x[i], v = y[i];
+        differ = differ || u.x != v.x || u.y != v.y || u.z != v.z || u.w != v.w;
+    }
+    if (__ballot(differ) != 0 && lane_id() == 0)
+        atomicOr(flag, 1u);
+}
+
+int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint64_t n,
+                          uint32_t* flag, hipStream_t stream)
+{
+    if (n == 0)
+        return JATAM_OK;
+    const uint64_t want = (n + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(records_differ_kernel, dim3(blocks), dim3(256), 0, stream,
+                       reinterpret_cast<const int4*>(x), reinterpret_cast<const int4*>(y), n,
+                       flag);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
 template <int TM>
-static void launch_stages(BatchArgs a, const bool classes[2], const int blocks[2][2],
+static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch launch[2],
                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
 {
-    constexpr int ti = TM == 2 ? 0 : 1;
     auto begin = [&](int s) {
         if (marks)
             (void)hipEventRecord(marks[2 * s], stream);
@@ -512,7 +632,9 @@ static void launch_stages(BatchArgs a, const bool classes[2], const int blocks[2
     for (int k = 0; k < 2; ++k) {
         if (!classes[k])
             continue;
-        const uint32_t nb = (uint32_t)blocks[k][ti];
+        const uint32_t nb = (uint32_t)launch[k].first_blocks;
+        const uint32_t rb = (uint32_t)launch[k].repeat_blocks;
+        a.refill = launch[k].refill;
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
         a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64);
         begin(kStageFirst + 3 * k);
@@ -523,19 +645,24 @@ static void launch_stages(BatchArgs a, const bool classes[2], const int blocks[2
         end(kStageFirst + 3 * k);
         begin(kStageSort + 3 * k);
         hipLaunchKernelGGL(sort_hist_kernel, dim3(nb), dim3(256), 0, stream, a, k);
-        hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(1024), 0, stream, a, k, nb);
+        const uint32_t entries = (uint32_t)kSizeBuckets * nb;
+        const uint32_t scan_blocks = (entries + kScanBlock - 1) / kScanBlock;
+        hipLaunchKernelGGL(sort_scan_kernel, dim3(scan_blocks), dim3(kScanBlock), 0, stream, a, k,
+                           entries);
+        hipLaunchKernelGGL(sort_scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, stream, a, k,
+                           scan_blocks);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nb), dim3(256), 0, stream, a, k);
         end(kStageSort + 3 * k);
         begin(kStageRepeat + 3 * k);
         if (k == 0)
-            hipLaunchKernelGGL((repeat_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
+            hipLaunchKernelGGL((repeat_kernel<16, TM>), dim3(rb), dim3(64), 0, stream, a, 0);
         else
-            hipLaunchKernelGGL((repeat_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
+            hipLaunchKernelGGL((repeat_kernel<32, TM>), dim3(rb), dim3(64), 0, stream, a, 1);
         end(kStageRepeat + 3 * k);
     }
 }
 
-int launch_batched(const BatchArgs& a, const bool classes[2], const int blocks[2][2], int tm,
+int launch_batched(const BatchArgs& a, const bool classes[2], const StageLaunch launch[2], int tm,
                    hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
 {
     if (launched)
@@ -543,9 +670,9 @@ int launch_batched(const BatchArgs& a, const bool classes[2], const int blocks[2
             launched[s] = 0;
     if (a.n > 0) {
         if (tm == 2)
-            launch_stages<2>(a, classes, blocks, stream, marks, launched);
+            launch_stages<2>(a, classes, launch, stream, marks, launched);
         else
-            launch_stages<4>(a, classes, blocks, stream, marks, launched);
+            launch_stages<4>(a, classes, launch, stream, marks, launched);
     }
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }

@@ -29,9 +29,12 @@ int launch_plain(const uint64_t* genomes, uint64_t first, int64_t n, const Param
 // ---------------------------------------------------------------------------
 enum {
     kCntCand = 0,     // [2] DET candidates per grid class (written by the sort)
+    kCntDiff = 2,     // record comparison flag of the autotuner
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
+constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
+constexpr int kMaxScanBlocks = 1024;
 
 // Device memory of a jatam_batch_t, sized for max_n genotypes per call and a
 // persistent grid of at most max_blocks one-wave blocks.
@@ -39,6 +42,7 @@ struct DeviceWorkspace {
     uint32_t* counters;       // kCntWords
     uint32_t* seg_count[2];   // [max_blocks] candidates staged by each wave
     uint32_t* seg_hist[2];    // [kSizeBuckets * max_blocks] bucket-major counts
+    uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
     uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks + 1)] per-wave segments
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
@@ -54,7 +58,9 @@ struct BatchArgs {
     int t, grid;                    // uniform t and G (range and list modes)
     int c, bits, runs;
     uint32_t key0, key1;
-    int refill;                     // idle lanes that trigger a refill (1..64)
+    const uint32_t* order;          // nullptr, or queue position -> input index
+    int narrow_max;                 // largest G classified with the 16 x 16 layout
+    int refill;                     // idle lanes that trigger a refill (1..64, per class)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
     jatam_result_t* out;
     unsigned long long* tally;      // nullptr or [4], accumulated
@@ -69,13 +75,25 @@ enum {
     kStages = 6,
 };
 
-// blocks[grid class][TM == 2 ? 0 : 1]: persistent grid of the stage kernels.
+// Launch parameters of one grid class: first-run refill threshold and the
+// persistent grids (one-wave blocks) of the first-run and repeat stages.
+struct StageLaunch {
+    int refill;
+    int first_blocks;
+    int repeat_blocks;
+};
+
+// occ[grid class][TM == 2 ? 0 : 1][0 first runs, 1 repeat runs]: resident
+// one-wave blocks per CU of the stage kernels.
+void batch_occupancy(int occ[2][2][2]);
+int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
 // When `marks` is not null, an event is recorded on the stream before stage
 // s (marks[2s]) and after it (marks[2s+1]), and launched[s] is set.
-int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
-void batch_persistent_blocks(int cus, int blocks[2][2]);
-int launch_batched(const BatchArgs& a, const bool classes[2], const int blocks[2][2], int tm,
+int launch_batched(const BatchArgs& a, const bool classes[2], const StageLaunch launch[2], int tm,
                    hipStream_t stream, hipEvent_t* marks, uint8_t* launched);
+// flag[0] |= 1 if the two record arrays differ anywhere.
+int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint64_t n,
+                          uint32_t* flag, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Genetic algorithm.
@@ -159,5 +177,11 @@ int launch_select_top(const float* scores, uint32_t n, uint32_t k, uint32_t* out
 
 int launch_gather(const uint64_t* src, const uint32_t* idx, uint32_t n, uint64_t* dst,
                   hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Shape histogram.
+// ---------------------------------------------------------------------------
+int launch_shape_hist(const jatam_result_t* recs, uint64_t n, jatam_shape_count_t* table,
+                      int log2cap, uint64_t* overflow, int cus, hipStream_t stream);
 
 }  // namespace jatam

@@ -99,6 +99,21 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_stage_times.restype = i32
         L.jatam_batch_stage_name.argtypes = [i32]
         L.jatam_batch_stage_name.restype = ctypes.c_char_p
+        L.jatam_batch_classify_items_ordered.argtypes = [vp, vp, vp, i64, i32, i32, u64, vp, vp,
+                                                         vp]
+        L.jatam_batch_classify_items_ordered.restype = i32
+        L.jatam_batch_get_tuning.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+        L.jatam_batch_get_tuning.restype = i32
+        L.jatam_batch_set_tuning.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+        L.jatam_batch_set_tuning.restype = i32
+        L.jatam_batch_autotune.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64, vp,
+                                           ctypes.POINTER(Tuning), vp]
+        L.jatam_batch_autotune.restype = i32
+        L.jatam_batch_autotune_log.argtypes = [vp, i32, ctypes.POINTER(Tuning),
+                                               ctypes.POINTER(ctypes.c_double)]
+        L.jatam_batch_autotune_log.restype = i32
+        L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
+        L.jatam_shape_histogram.restype = i32
         _lib = L
     return _lib
 
@@ -201,6 +216,52 @@ def ga_offspring(pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
 ITEM_BYTES = 24
 
 
+class Tuning(ctypes.Structure):
+    """jatam_tuning_t: launch parameters of one grid class."""
+    _fields_ = [("refill", ctypes.c_int), ("first_waves", ctypes.c_int),
+                ("repeat_waves", ctypes.c_int), ("wide_layout", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SHAPE_COUNT_BYTES = 16
+
+
+def shape_histogram(records: torch.Tensor, table: torch.Tensor | None = None,
+                    capacity: int = 4096, overflow: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """jatam_shape_histogram: adds the DET records to a device table of
+    jatam_shape_count_t entries, held as an int64 tensor (capacity, 2)
+    [hash | size << 32, count]; a new zeroed table if none is given."""
+    if records.dtype != torch.int32 or records.dim() != 2 or records.shape[1] != 4 \
+            or not records.is_cuda or not records.is_contiguous():
+        raise ValueError("records must be a contiguous device int32 tensor (n, 4)")
+    if table is None:
+        table = torch.zeros((capacity, 2), dtype=torch.int64, device=records.device)
+    if table.dtype != torch.int64 or table.dim() != 2 or table.shape[1] != 2 \
+            or not table.is_cuda or not table.is_contiguous():
+        raise ValueError("table must be a contiguous device int64 tensor (capacity, 2)")
+    if overflow is not None and (overflow.dtype != torch.int64 or overflow.numel() != 1):
+        raise ValueError("overflow must be a device int64 tensor of one element")
+    rc = lib().jatam_shape_histogram(records.data_ptr(), records.shape[0], table.data_ptr(),
+                                     table.shape[0],
+                                     overflow.data_ptr() if overflow is not None else None,
+                                     _stream_handle(stream))
+    _check(rc, "jatam_shape_histogram")
+    return table
+
+
+def shape_table_to_numpy(table: torch.Tensor):
+    """Non-empty entries of a shape table as a numpy structured array
+    (hash uint32, size int32, count uint64), sorted by (size, hash)."""
+    import numpy as np
+    dt = np.dtype([("hash", "<u4"), ("size", "<i4"), ("count", "<u8")])
+    arr = table.cpu().numpy().view(dt).reshape(-1)
+    arr = arr[arr["size"] != 0]
+    return np.sort(arr, order=("size", "hash"))
+
+
 def make_items(genomes, t, grid, rng_ids=None):
     """Packs per-item genomes, tile counts and grids (numpy arrays) into the
     24-byte jatam_item_t layout; returns a uint8 numpy array of shape (n, 24)."""
@@ -286,19 +347,63 @@ class Batch:
 
     def classify_items(self, items: torch.Tensor, c: int = 8, runs: int = 20, seed: int = 1,
                        out: torch.Tensor | None = None, tally: torch.Tensor | None = None,
-                       stream=None) -> torch.Tensor:
-        """jatam_batch_classify_items; items is a device uint8 tensor (n, 24)."""
+                       order: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """jatam_batch_classify_items (or _ordered, given a queue order);
+        items is a device uint8 tensor (n, 24), order a device int32 tensor
+        (n,) holding a permutation of 0..n-1."""
         if items.dtype != torch.uint8 or items.dim() != 2 or items.shape[1] != ITEM_BYTES:
             raise ValueError("items must be a uint8 tensor of shape (n, 24)")
         if not items.is_cuda or not items.is_contiguous():
             raise ValueError("items must be a contiguous device tensor")
         n = items.shape[0]
         rec = _records(n, items.device, out)
-        rc = lib().jatam_batch_classify_items(self._h, items.data_ptr(), n, c, runs, seed,
-                                              rec.data_ptr(), self._tally_ptr(tally),
-                                              _stream_handle(stream))
+        if order is None:
+            rc = lib().jatam_batch_classify_items(self._h, items.data_ptr(), n, c, runs, seed,
+                                                  rec.data_ptr(), self._tally_ptr(tally),
+                                                  _stream_handle(stream))
+        else:
+            if order.dtype not in (torch.int32, torch.uint32) or tuple(order.shape) != (n,) \
+                    or not order.is_cuda or not order.is_contiguous():
+                raise ValueError("order must be a contiguous device int32 tensor of shape (n,)")
+            rc = lib().jatam_batch_classify_items_ordered(self._h, items.data_ptr(),
+                                                          order.data_ptr(), n, c, runs, seed,
+                                                          rec.data_ptr(), self._tally_ptr(tally),
+                                                          _stream_handle(stream))
         _check(rc, "jatam_batch_classify_items")
         return rec
+
+    def get_tuning(self, grid_limit: int) -> dict:
+        t = Tuning()
+        _check(lib().jatam_batch_get_tuning(self._h, grid_limit, ctypes.byref(t)),
+               "jatam_batch_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, grid_limit: int, **fields) -> None:
+        t = Tuning()
+        _check(lib().jatam_batch_get_tuning(self._h, grid_limit, ctypes.byref(t)),
+               "jatam_batch_get_tuning")
+        for k, v in fields.items():
+            setattr(t, k, int(v))
+        _check(lib().jatam_batch_set_tuning(self._h, grid_limit, ctypes.byref(t)),
+               "jatam_batch_set_tuning")
+
+    def autotune(self, first: int, n: int, t: int, c: int = 8, grid_limit: int = 16,
+                 runs: int = 20, seed: int = 1, stream=None):
+        """jatam_batch_autotune over [first, first + n); returns (best
+        parameters, [(parameters, median ms), ...] in the order tried)."""
+        scratch = torch.empty((2 * n, 4), dtype=torch.int32, device="cuda")
+        best = Tuning()
+        rc = lib().jatam_batch_autotune(self._h, first, n, t, c, grid_limit, runs, seed,
+                                        scratch.data_ptr(), ctypes.byref(best),
+                                        _stream_handle(stream))
+        _check(rc, "jatam_batch_autotune")
+        log = []
+        count = lib().jatam_batch_autotune_log(self._h, -1, None, None)
+        for i in range(count):
+            e, ms = Tuning(), ctypes.c_double()
+            lib().jatam_batch_autotune_log(self._h, i, ctypes.byref(e), ctypes.byref(ms))
+            log.append((e.as_dict(), ms.value))
+        return best.as_dict(), log
 
     def ga_step(self, pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
                 generation: int, c: int = 8, grid_limit: int = 32, runs: int = 20,

@@ -49,13 +49,24 @@ def slice_summary(recs, s0, e0, c0, runs):
     }
 
 
+def shape_counts(recs):
+    """{(hash, size): count} over the DET records."""
+    det = recs[recs["cls"] == 3]
+    keys, counts = np.unique(np.stack([det["hash"].astype(np.int64), det["size"].astype(np.int64)]),
+                             axis=1, return_counts=True)
+    return {(int(h), int(z)): int(c) for (h, z), c in zip(keys.T, counts)}
+
+
 def make(t, grid, runs, seed, total, slice_n, path):
     t0 = time.time()
     slices = []
+    shapes = {}
     for first in range(0, total, slice_n):
         n = min(slice_n, total - first)
         recs, s0, e0, c0 = ref.classify_range_run0(first, n, t, grid=grid, runs=runs, seed=seed)
         s = slice_summary(recs, s0, e0, c0, runs)
+        for key, cnt in shape_counts(recs).items():
+            shapes[key] = shapes.get(key, 0) + cnt
         s["first"] = first
         s["n"] = n
         slices.append(s)
@@ -68,6 +79,8 @@ def make(t, grid, runs, seed, total, slice_n, path):
         "steps": sum(s["steps"] for s in slices),
         "det_size": sum(s["det_size"] for s in slices),
         "work": {k: sum(s["work"][k] for s in slices) for k in slices[0]["work"]},
+        "shapes": [{"hash": h, "size": z, "count": shapes[(h, z)]}
+                   for (h, z) in sorted(shapes, key=lambda k: (k[1], k[0]))],
     }
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)

@@ -69,3 +69,10 @@ def test_range_beyond_space_rejected(lib):
 def test_empty_call_launches_nothing(lib):
     assert lib.jatam_classify(None, 0, 2, 8, 16, 20, 1, None, None) == 0
     assert lib.jatam_classify_range(0, 0, 2, 8, 16, 20, 1, None, None) == 0
+
+
+@pytest.mark.parametrize("n,capacity", [(-1, 1024), (1, 0), (1, 100), (1, 32), (1, 1 << 25)])
+def test_shape_histogram_rejects_bad_arguments(lib, n, capacity):
+    recs = ctypes.create_string_buffer(16)
+    table = ctypes.create_string_buffer(16 * 64)
+    assert lib.jatam_shape_histogram(recs, n, table, capacity, None, None) == -1

@@ -1,0 +1,127 @@
+"""Launch parameters of the pipeline: the autotuner and explicit tunings never
+change a record, and neither does the order of the item queue (including an
+order by the surrogate's predicted cost).  Records are checked against the
+oracle or its golden digests."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def jt():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    import paper_2205_15311_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def records(rec):
+    torch.cuda.synchronize()
+    return rec.cpu().numpy().view(ref.RECORD).reshape(-1)
+
+
+def assert_same(got, want, label):
+    bad = np.nonzero(got != want)[0]
+    if len(bad):
+        lines = [f"{label}: {len(bad)} of {len(want)} records differ"]
+        for i in bad[:8]:
+            lines.append(f"  [{i}] gpu={tuple(got[i])} oracle={tuple(want[i])}")
+        pytest.fail("\n".join(lines))
+
+
+def test_autotune_on_s28_keeps_the_golden_records(jt):
+    with open(os.path.join(HERE, "golden", "s28_digests.json")) as f:
+        gold = json.load(f)
+    n = gold["slice"]
+    with jt.Batch(1 << 22) as b:
+        best, log = b.autotune(0, 1 << 22, 2, 8, 16, 20, 1)
+        print("autotune:", best, [(e, round(ms, 3)) for e, ms in log], flush=True)
+        assert len(log) >= 8
+        best_ms = [ms for e, ms in log if e == best][-1]
+        assert best_ms <= log[0][1]          # never worse than where it started
+        assert b.get_tuning(16) == best
+        out = torch.empty((4 * n, 4), dtype=torch.int32, device="cuda")
+        b.classify_range(0, 4 * n, 2, 8, 16, 20, 1, out=out)
+        rec = out.cpu().numpy()
+    for s in gold["slices"][:4]:
+        blob = rec[s["first"]:s["first"] + s["n"]].tobytes()
+        assert hashlib.sha256(blob).hexdigest() == s["sha256"], s["first"]
+
+
+@pytest.mark.parametrize("grid,tuning", [
+    (16, dict(refill=1, first_waves=1, repeat_waves=1)),
+    (16, dict(refill=64, first_waves=3, repeat_waves=2)),
+    (16, dict(wide_layout=1)),
+    (32, dict(refill=8, first_waves=1, repeat_waves=2)),
+])
+def test_explicit_tunings_keep_records(jt, grid, tuning):
+    rng = np.random.default_rng(grid + len(tuning))
+    g = rng.integers(0, 1 << 36, size=20_000, dtype=np.uint64)
+    with jt.Batch(1 << 16) as b:
+        b.set_tuning(grid, **tuning)
+        got = records(b.classify(torch.from_numpy(g.view(np.int64)).cuda(), 3, 8, grid, 20, 1))
+    assert_same(got, ref.classify(g, 3, grid=grid, runs=20, seed=1), f"G={grid} {tuning}")
+
+
+def test_bad_tunings_rejected(jt):
+    with jt.Batch(1024) as b:
+        for bad in (dict(refill=0), dict(refill=65), dict(first_waves=0), dict(repeat_waves=0),
+                    dict(wide_layout=2)):
+            with pytest.raises(jt.JatamError):
+                b.set_tuning(16, **bad)
+        with pytest.raises(jt.JatamError):
+            b.set_tuning(32, wide_layout=1)
+
+
+def mixed_items(jt, n):
+    g, t, grid = inputs.mixed_stream(n, key=17)
+    items = np.zeros(n, dtype=ref.ITEM)
+    items["genome"], items["t"], items["grid"] = g, t, grid
+    items["rng_id"] = g | (t.astype(np.uint64) << np.uint64(56))
+    return g, t, grid, items
+
+
+def test_queue_order_does_not_change_records(jt):
+    n = 1 << 15
+    g, t, grid, items = mixed_items(jt, n)
+    want = ref.classify_items(items)
+    dev = torch.from_numpy(jt.make_items(g, t, grid)).cuda()
+    rng = np.random.default_rng(4)
+    orders = {"identity": np.arange(n), "reversed": np.arange(n)[::-1].copy(),
+              "random": rng.permutation(n), "grid-major": np.argsort(-grid.astype(np.int64),
+                                                                     kind="stable")}
+    with jt.Batch(n) as b:
+        for name, order in orders.items():
+            tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+            o = torch.from_numpy(order.astype(np.int32)).cuda()
+            got = records(b.classify_items(dev, 8, 20, 1, tally=tally, order=o))
+            assert_same(got, want, name)
+            assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
+
+
+def test_surrogate_cost_order_keeps_records(jt):
+    """The queue ordered by the surrogate's predicted cost (log1p size, most
+    expensive first): records equal the oracle's."""
+    n = 1 << 15
+    g, t, grid, items = mixed_items(jt, n)
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    dt = torch.from_numpy(t.astype(np.uint8)).cuda()
+    with jt.MLP(4096) as net, jt.Batch(n) as b:
+        net.init(5)
+        cost = net.forward(dg, dt)[:, 3]
+        order = torch.argsort(cost, descending=True).to(torch.int32).contiguous()
+        dev = torch.from_numpy(jt.make_items(g, t, grid)).cuda()
+        got = records(b.classify_items(dev, 8, 20, 1, order=order))
+    assert_same(got, ref.classify_items(items), "surrogate order")
