@@ -2,11 +2,14 @@
 """Benchmark: genotypes classified per second over the whole of S_{2,8}.
 
 One step = classification of all 2^24 two-tile genotypes (c=8, G=16, R=20,
-seed 1), no input read from HBM, 256 MiB of records written to HBM.  Two
+seed 1), no input read from HBM, 256 MiB of records written to HBM.  Three
 paths are timed on the same stream:
   plain    16 launches of the plain kernel over 2^20-genotype ranges,
+  graph    one captured pipeline of a 2^20-genotype slice, replayed 16 times,
   batched  one pipelined call over the whole range (first runs with lane
            refill, size-ordered repeat runs; the reported value).
+The pipeline's launch parameters come from the library's autotuner, run
+(untimed) on the first 2^22 genotypes before timing.
 After timing, each path's records are hashed per 2^20 slice and compared
 with the oracle's digests (tests/golden/s28_digests.json), so a rate counts
 only if it is bit-exact.
@@ -104,6 +107,98 @@ def cpu_baseline(threads):
                       f"{dt:.1f} s wall on {threads} threads)"}
 
 
+def ga_report(args, jt, torch):
+    """The surrogate-screened GA against the plain GA at an equal number of
+    generations: three-tile genotypes, c=8, G=32, R=20, population 65,536,
+    tournament 4, per-edge crossover, mutation 1/12; the surrogate trained
+    on exact classifications of 2^24 uniform three-tile genotypes; offspring
+    oversampled 4x and screened.  Prints one JSON line."""
+    import numpy as np
+    from tests import inputs
+    n, t, grid = 65_536, 3, 32
+    gens = args.generations
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def elapsed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    # training data: exact classifications from the batched path
+    ntrain = 1 << 24
+    train = torch.from_numpy(inputs.three_tile_sample(ntrain).view(np.int64)).to(dev)
+    with jt.Batch(ntrain) as b:
+        labels = b.classify(train, t, C, grid, RUNS, SEED)
+        torch.cuda.synchronize()
+    net = jt.MLP(4096)
+    net.init(1)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def train_epoch():
+        for lo in range(0, ntrain, 4096):
+            net.train_step(train[lo:lo + 4096], t, labels[lo:lo + 4096], lr=1e-3, loss=loss)
+
+    train_s = elapsed(train_epoch)
+    final_loss = float(loss.item())
+    del train, labels
+
+    params = jt.GAParams(seed=5, tournament=4, mut_num=1, mut_den=12)
+    pop0 = torch.from_numpy(inputs.population(n, t).view(np.int64)).to(dev)
+    results = {}
+    with jt.Batch(n) as b, jt.GA(4 * n) as ga:
+        rec = b.classify(pop0, t, C, grid, RUNS, SEED)
+        fit0 = torch.where(rec[:, 0] == 3, rec[:, 1], torch.zeros_like(rec[:, 1])).contiguous()
+        for mode in ("plain", "screened"):
+            best = torch.zeros(gens + 1, dtype=torch.int32, device=dev)
+            mean = torch.zeros(gens + 1, dtype=torch.float32, device=dev)
+            state = {"pop": pop0.clone(), "fit": fit0.clone()}
+            best[0] = fit0.max()
+            mean[0] = fit0.float().mean()
+
+            def run():
+                for g in range(gens):
+                    if mode == "plain":
+                        p, f = b.ga_step(state["pop"], state["fit"], t, params, g,
+                                         grid_limit=grid, runs=RUNS, seed=SEED)
+                    else:
+                        p, f = ga.step_screened(b, net, state["pop"], state["fit"], t, params, g,
+                                                oversample=4, grid_limit=grid, runs=RUNS,
+                                                seed=SEED)
+                    state["pop"], state["fit"] = p, f
+                    best[g + 1] = f.max()
+                    mean[g + 1] = f.float().mean()
+
+            secs = elapsed(run)
+            bl, ml = best.cpu().tolist(), mean.cpu().tolist()
+            marks = sorted(set([0, 1, 10, 50, 100, 200, 300, 400, gens]) & set(range(gens + 1)))
+            results[mode] = {
+                "exact_evals_per_s": n * gens / secs,
+                "candidates_scored_per_s": (4 * n * gens / secs) if mode == "screened" else 0,
+                "ms_per_generation": secs * 1e3 / gens,
+                "best_fitness": {str(g): bl[g] for g in marks},
+                "mean_fitness": {str(g): round(ml[g], 4) for g in marks},
+            }
+    net.close()
+    line = {
+        "metric": "GA exact evaluations/s, t=3 c=8 G=32 R=20, population 65536 "
+                  "(surrogate-screened vs plain, equal generations)",
+        "value": results["screened"]["exact_evals_per_s"],
+        "unit": "exact evaluations/s",
+        "n_gpus": 1, "generations": gens, "higher_is_better": True,
+        "data": "synthetic: uniform random three-tile population and training genotypes "
+                "(numpy Philox keys 5 and 11)",
+        "surrogate": {"train_genotypes": ntrain, "train_epoch_s": train_s,
+                      "final_batch_loss": final_loss},
+        "paths": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +207,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = all usable cores, at most 16)")
+    ap.add_argument("--workload", choices=("enumeration", "ga"), default="enumeration",
+                    help="ga: the surrogate-screened GA report instead of the benchmark")
+    ap.add_argument("--generations", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 blits and 4 elementwise copies of 256 MiB "
                          "(to scale HBM counters)")
@@ -129,6 +227,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     jt.lib()
+    if args.workload == "ga":
+        ga_report(args, jt, torch)
+        return
     if args.copy_calibration:
         # a blit (copy_) and an elementwise kernel (neg), each reading and
         # writing 256 MiB per launch
@@ -164,6 +265,11 @@ def main():
 
     def batched_step():
         batch.classify_range(0, TOTAL, T, C, GRID, RUNS, SEED, out=out, stream=stream)
+
+    graph_batch = jt.Batch(SLICE)
+
+    def graph_step():
+        graph_batch.enumerate(0, SLICE, nslices, T, C, GRID, RUNS, SEED, out=out, stream=stream)
 
     def verify():
         rec = out.cpu().numpy()
@@ -206,6 +312,17 @@ def main():
     plain_mean_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
     plain_value = TOTAL * args.steps / (plain_total_ms / 1e3)
 
+    # launch parameters chosen by the library's autotuner on the first 2^22
+    # genotypes (untimed; it rejects any candidate that changes a record)
+    tuning, tune_log = batch.autotune(0, 1 << 22, T, C, GRID, RUNS, SEED)
+    graph_batch.set_tuning(GRID, **tuning)
+
+    # graph path: one captured 2^20-genotype slice pipeline, replayed 16 times
+    graph_total_ms, _ = timed(graph_step, graph_step)
+    graph_ok = verify()
+    graph_value = TOTAL * args.steps / (graph_total_ms / 1e3)
+    graph_batch.close()
+
     # batched path: one call per step, stage events recorded by the library
     batch.set_timing(True)
     batched_total_ms, _ = timed(batched_step, batched_step)
@@ -221,7 +338,7 @@ def main():
     achieved = ops[dominant] / dom_s
     plain_ops_per_launch = algorithmic_ops(SLICE, gold["steps"] / nslices,
                                            gold["tally"][3] / nslices, gold["det_size"] / nslices)
-    bit_exact = plain_ok and batched_ok
+    bit_exact = plain_ok and batched_ok and graph_ok
     line = {
         "metric": METRIC,
         "value": batched_value if batched_ok else 0.0,
@@ -238,12 +355,16 @@ def main():
         "config": {"workload": "S_2,8 full enumeration, t=2 c=8 G=16 R=20 seed=1, "
                                "one pipelined call over 2^24 genotypes per step",
                    "genotypes_per_step": TOTAL, "t": T, "c": C, "grid": GRID, "runs": RUNS,
-                   "seed": SEED},
+                   "seed": SEED, "tuning": tuning,
+                   "autotune_ms": [round(ms, 4) for _, ms in tune_log]},
         "bit_exact": bool(bit_exact),
         "paths": {
             "batched": {"value": batched_value, "ms_per_step": batched_total_ms / args.steps,
                         "bit_exact": batched_ok, "surrogate": False,
                         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
+            "graph": {"value": graph_value, "ms_per_step": graph_total_ms / args.steps,
+                      "bit_exact": graph_ok,
+                      "kernel": "one captured 2^20-genotype slice pipeline, 16 hipGraph replays"},
             "plain": {"value": plain_value, "ms_per_step": plain_total_ms / args.steps,
                       "bit_exact": plain_ok, "mean_launch_ms": plain_mean_launch_s * 1e3,
                       "kernel": "classify_plain_kernel<16,256>, 2^20 genotypes per launch",

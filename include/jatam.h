@@ -119,6 +119,15 @@ int jatam_classify_range(uint64_t first, int64_t n, int t, int c, int grid_limit
  * concurrently.
  * ------------------------------------------------------------------------ */
 
+/* One entry of a shape histogram (jatam_shape_histogram): a deterministic
+ * shape (its D4 hash and size) and how many DET records have it.  size == 0
+ * marks an empty entry. */
+typedef struct {
+    uint32_t hash;
+    int32_t  size;
+    uint64_t count;
+} jatam_shape_count_t;   /* 16 bytes */
+
 /* One genotype of a mixed stream: its own tile count, grid and RNG stream. */
 typedef struct {
     uint64_t genome;   /* genome layout above, t tiles                        */
@@ -159,6 +168,29 @@ int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, 
 int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, int64_t n,
                                int c, int runs, uint64_t seed, jatam_result_t* out,
                                uint64_t* tally, void* stream);
+
+/*
+ * Enumeration of a lexicographic range in slices, with HIP graphs: the
+ * pipeline of one slice of `slice` genotypes (and, if `shapes` is given, the
+ * shape histogram of its records) is captured once into a graph whose
+ * kernels read the slice number from a device counter, then the graph is
+ * launched `slices` times on `stream`, the counter advancing by one per
+ * replay.  Covers genotypes first .. first + slice*slices - 1 (§3.4: the
+ * paper's slice-by-slice enumeration, here without host work per slice).
+ *   out     device, slice*slices records in genotype order, or NULL to keep
+ *           only the tally and the histogram (records of each slice then go
+ *           to the workspace and are overwritten by the next slice)
+ *   tally   NULL or device uint64[4], ADDED to (as jatam_batch_classify)
+ *   shapes, shapes_capacity
+ *           NULL, or a table as for jatam_shape_histogram, ADDED to
+ * 1 <= slice <= the workspace's max_n.  The graph is kept in the workspace
+ * until the next enumeration or destroy (which first wait for it); calls on
+ * one workspace must be serialised as for every other call.
+ */
+int jatam_batch_enumerate(jatam_batch_t* batch, uint64_t first, int64_t slice, int64_t slices,
+                          int t, int c, int grid_limit, int runs, uint64_t seed,
+                          jatam_result_t* out, uint64_t* tally, jatam_shape_count_t* shapes,
+                          int64_t shapes_capacity, void* stream);
 
 /*
  * Mixed items taken in the order of a queue: position p of the queue holds
@@ -367,14 +399,6 @@ int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* ml
  * slice, on the host, while the next slice is classified).  Kept on the
  * device here.
  * ------------------------------------------------------------------------ */
-
-/* One entry: a deterministic shape (its D4 hash and size) and how many DET
- * records have it.  size == 0 marks an empty entry. */
-typedef struct {
-    uint32_t hash;
-    int32_t  size;
-    uint64_t count;
-} jatam_shape_count_t;   /* 16 bytes */
 
 /*
  * Adds the DET records of recs[0..n) to a shape histogram.

@@ -19,6 +19,11 @@ struct jatam_batch {
     jatam::DeviceWorkspace ws;
     void* allocations[20];
     int nalloc;
+    // graph of the last enumeration (kept until the next one or destroy)
+    hipStream_t capture_stream;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    hipStream_t graph_stream;
     // timing hook: one set of stage events per call made while enabled
     bool timing;
     std::vector<hipEvent_t> marks;        // 2 * kStages per recorded call
@@ -129,9 +134,22 @@ static void drop_marks(jatam_batch_t* b)
     b->launched.clear();
 }
 
+static void drop_graph(jatam_batch_t* b)
+{
+    if (b->graph_exec != nullptr)
+        (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph != nullptr)
+        (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
+
 static void free_batch(jatam_batch_t* b)
 {
     drop_marks(b);
+    drop_graph(b);
+    if (b->capture_stream != nullptr)
+        (void)hipStreamDestroy(b->capture_stream);
     for (int i = 0; i < b->nalloc; ++i)
         (void)hipFree(b->allocations[i]);
     delete b;
@@ -157,15 +175,10 @@ static int next_marks(jatam_batch_t* b, hipEvent_t** marks, uint8_t** launched)
 }
 
 // Launches the pipeline.  grid_limit: the uniform G of the call, or 0 for
-// mixed items (both grid classes).
-static int launch_timed(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
-                        hipStream_t stream)
+// mixed items (both grid classes).  marks/launched: timing hook or nullptr.
+static int launch_pipeline(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
+                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
 {
-    hipEvent_t* marks;
-    uint8_t* launched;
-    const int rc = next_marks(b, &marks, &launched);
-    if (rc != JATAM_OK)
-        return rc;
     const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
     a.narrow_max = b->tune[0].wide_layout ? 0 : 16;
     const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
@@ -178,6 +191,17 @@ static int launch_timed(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, in
         launch[k] = jatam::StageLaunch{t.refill, fw * b->cus, rw * b->cus};
     }
     return jatam::launch_batched(a, classes, launch, tm, stream, marks, launched);
+}
+
+static int launch_timed(jatam_batch_t* b, const jatam::BatchArgs& a, int grid_limit, int max_t,
+                        hipStream_t stream)
+{
+    hipEvent_t* marks;
+    uint8_t* launched;
+    const int rc = next_marks(b, &marks, &launched);
+    if (rc != JATAM_OK)
+        return rc;
+    return launch_pipeline(b, a, grid_limit, max_t, stream, marks, launched);
 }
 
 static bool batch_alloc(jatam_batch_t* b, size_t bytes, void** out)
@@ -201,6 +225,10 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->max_n = max_n;
     b->nalloc = 0;
     b->timing = false;
+    b->capture_stream = nullptr;
+    b->graph = nullptr;
+    b->graph_exec = nullptr;
+    b->graph_stream = nullptr;
     for (int k = 0; k < 2; ++k)
         b->tune[k] = jatam_tuning_t{24, 64, 64, 0};
     hipDeviceProp_t prop;
@@ -211,6 +239,12 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     }
     b->cus = prop.multiProcessorCount;
     jatam::batch_occupancy(b->occ);
+    // a stream of its own to capture enumeration graphs on (default priority)
+    if (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        b->capture_stream = nullptr;
+        free_batch(b);
+        return JATAM_E_HIP;
+    }
     // first-run grids set the number of staging segments
     int max_blocks = 1;
     for (int k = 0; k < 2; ++k)
@@ -292,6 +326,8 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.key0 = p.key0;
     a.key1 = p.key1;
     a.order = nullptr;
+    a.slice = nullptr;
+    a.out_per_slice = 0;
     a.narrow_max = 16;
     a.refill = 24;
     a.seg_cap = 0;
@@ -364,6 +400,79 @@ int jatam_batch_classify_items_ordered(jatam_batch_t* batch, const jatam_item_t*
     a.items = items;
     a.order = order;
     return launch_timed(batch, a, 0, 4, (hipStream_t)stream);
+}
+
+int jatam_batch_enumerate(jatam_batch_t* batch, uint64_t first, int64_t slice, int64_t slices,
+                          int t, int c, int grid_limit, int runs, uint64_t seed,
+                          jatam_result_t* out, uint64_t* tally, jatam_shape_count_t* shapes,
+                          int64_t shapes_capacity, void* stream)
+{
+    jatam::Params p;
+    int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    if (rc != JATAM_OK)
+        return rc;
+    if (batch == nullptr || slice < 1 || slice > batch->max_n || slices < 1 ||
+        slices > (int64_t)0xFFFFFFFFu)
+        return JATAM_E_INVALID_ARG;
+    if ((rc = batch_check(batch, slice, batch)) != JATAM_OK)
+        return rc;
+    const uint64_t total = (uint64_t)slice * (uint64_t)slices;
+    if (total / (uint64_t)slices != (uint64_t)slice)
+        return JATAM_E_INVALID_ARG;
+    const uint64_t last = first + (total - 1);
+    if (last < first || (p.genome_bits < 64 && (last >> p.genome_bits) != 0))
+        return JATAM_E_INVALID_ARG;
+    int log2cap = 0;
+    if (shapes != nullptr) {
+        if (shapes_capacity < 64 || shapes_capacity > (1 << 24) ||
+            (shapes_capacity & (shapes_capacity - 1)) != 0)
+            return JATAM_E_INVALID_ARG;
+        while ((int64_t(1) << log2cap) < shapes_capacity)
+            ++log2cap;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the previous enumeration's graph may still run: wait for it, then drop it
+    if (batch->graph_exec != nullptr) {
+        if (hipStreamSynchronize(batch->graph_stream) != hipSuccess)
+            return JATAM_E_HIP;
+        drop_graph(batch);
+    }
+    jatam::BatchArgs a = batch_args(batch, p, slice, out != nullptr ? out : batch->ws.records,
+                                    tally);
+    a.first = first;
+    a.slice = batch->ws.counters + jatam::kCntSlice;
+    a.out_per_slice = out != nullptr;
+    // capture one slice: pipeline, shape histogram of its records, counter + 1
+    hipStream_t cs = batch->capture_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return JATAM_E_HIP;
+    rc = launch_pipeline(batch, a, grid_limit, t, cs, nullptr, nullptr);
+    if (rc == JATAM_OK && shapes != nullptr)
+        rc = jatam::launch_shape_hist(a.out, (uint64_t)slice, shapes, log2cap, nullptr,
+                                      batch->cus, out != nullptr ? a.slice : nullptr, cs);
+    if (rc == JATAM_OK)
+        rc = jatam::launch_slice_advance(batch->ws.counters + jatam::kCntSlice, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != JATAM_OK || ec != hipSuccess || graph == nullptr) {
+        if (graph != nullptr)
+            (void)hipGraphDestroy(graph);
+        return rc != JATAM_OK ? rc : JATAM_E_HIP;
+    }
+    batch->graph = graph;
+    if (hipGraphInstantiate(&batch->graph_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        batch->graph_exec = nullptr;
+        drop_graph(batch);
+        return JATAM_E_HIP;
+    }
+    batch->graph_stream = s;
+    // replay it once per slice, the counter starting at 0
+    if (jatam::launch_slice_reset(batch->ws.counters + jatam::kCntSlice, s) != JATAM_OK)
+        return JATAM_E_HIP;
+    for (int64_t k = 0; k < slices; ++k)
+        if (hipGraphLaunch(batch->graph_exec, s) != hipSuccess)
+            return JATAM_E_HIP;
+    return JATAM_OK;
 }
 
 int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes)
@@ -944,6 +1053,6 @@ extern "C" int jatam_shape_histogram(const jatam_result_t* recs, int64_t n,
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return JATAM_E_HIP;
-    return jatam::launch_shape_hist(recs, (uint64_t)n, table, log2cap, overflow, cus,
+    return jatam::launch_shape_hist(recs, (uint64_t)n, table, log2cap, overflow, cus, nullptr,
                                     (hipStream_t)stream);
 }

@@ -69,6 +69,33 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint32_t i)
     return g;
 }
 
+// A graph-replayed enumeration reads its slice from the device: the call
+// covers genotypes first + s*n .. and writes records at out + s*n if asked.
+__device__ __forceinline__ void apply_slice(BatchArgs& a)
+{
+    if (a.slice != nullptr) {
+        const uint64_t s = *a.slice;
+        a.first += s * (uint64_t)a.n;
+        if (a.out_per_slice)
+            a.out += s * (uint64_t)a.n;
+    }
+}
+
+__global__ void slice_reset_kernel(uint32_t* counter) { counter[0] = 0; }
+__global__ void slice_advance_kernel(uint32_t* counter) { counter[0] += 1; }
+
+int launch_slice_reset(uint32_t* counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(slice_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+int launch_slice_advance(uint32_t* counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(slice_advance_kernel, dim3(1), dim3(1), 0, stream, counter);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
 // Grid class of a genotype: 0 = the 16 x 16 layout, 1 = the 32 x 32 layout.
 __device__ __forceinline__ int grid_class(const BatchArgs& a, int grid)
 {
@@ -139,6 +166,7 @@ template <int W, int TM>
 __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
+    apply_slice(a);
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t ring[kRing];
     __shared__ uint4 cache_mem[kShapeCache];
@@ -416,6 +444,7 @@ template <int W, int TM>
 __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
+    apply_slice(a);
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t orient[8][64];   // per group: the 8 orientation hashes
     __shared__ uint4 cache_mem[kShapeCache];

@@ -30,6 +30,7 @@ int launch_plain(const uint64_t* genomes, uint64_t first, int64_t n, const Param
 enum {
     kCntCand = 0,     // [2] DET candidates per grid class (written by the sort)
     kCntDiff = 2,     // record comparison flag of the autotuner
+    kCntSlice = 3,    // slice counter of a graph-replayed enumeration
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
@@ -59,6 +60,9 @@ struct BatchArgs {
     int c, bits, runs;
     uint32_t key0, key1;
     const uint32_t* order;          // nullptr, or queue position -> input index
+    const uint32_t* slice;          // nullptr, or device slice counter s: the call
+                                    // covers first + s*n .. (graph replays)
+    int out_per_slice;              // with `slice`: records go to out + s*n
     int narrow_max;                 // largest G classified with the 16 x 16 layout
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
@@ -91,6 +95,9 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
 // s (marks[2s]) and after it (marks[2s+1]), and launched[s] is set.
 int launch_batched(const BatchArgs& a, const bool classes[2], const StageLaunch launch[2], int tm,
                    hipStream_t stream, hipEvent_t* marks, uint8_t* launched);
+// Slice counter of a replayed enumeration: set to 0, or advanced by one.
+int launch_slice_reset(uint32_t* counter, hipStream_t stream);
+int launch_slice_advance(uint32_t* counter, hipStream_t stream);
 // flag[0] |= 1 if the two record arrays differ anywhere.
 int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint64_t n,
                           uint32_t* flag, hipStream_t stream);
@@ -181,7 +188,10 @@ int launch_gather(const uint64_t* src, const uint32_t* idx, uint32_t n, uint64_t
 // ---------------------------------------------------------------------------
 // Shape histogram.
 // ---------------------------------------------------------------------------
+// slice: nullptr, or a device slice counter s: the records read are
+// recs + s * n (graph replays of an enumeration).
 int launch_shape_hist(const jatam_result_t* recs, uint64_t n, jatam_shape_count_t* table,
-                      int log2cap, uint64_t* overflow, int cus, hipStream_t stream);
+                      int log2cap, uint64_t* overflow, int cus, const uint32_t* slice,
+                      hipStream_t stream);
 
 }  // namespace jatam

@@ -46,8 +46,11 @@ __device__ __forceinline__ bool global_add(jatam_shape_count_t* table, int log2c
 __global__ __launch_bounds__(kHistThreads) void shape_hist_kernel(const jatam_result_t* __restrict__ recs,
                                                                   uint64_t n,
                                                                   jatam_shape_count_t* table,
-                                                                  int log2cap, uint64_t* overflow)
+                                                                  int log2cap, uint64_t* overflow,
+                                                                  const uint32_t* slice)
 {
+    if (slice != nullptr)
+        recs += (uint64_t)*slice * n;
     __shared__ unsigned long long keys[kHistLocal];
     __shared__ uint32_t counts[kHistLocal];
     for (int i = threadIdx.x; i < kHistLocal; i += kHistThreads) {
@@ -89,7 +92,8 @@ __global__ __launch_bounds__(kHistThreads) void shape_hist_kernel(const jatam_re
 }
 
 int launch_shape_hist(const jatam_result_t* recs, uint64_t n, jatam_shape_count_t* table,
-                      int log2cap, uint64_t* overflow, int cus, hipStream_t stream)
+                      int log2cap, uint64_t* overflow, int cus, const uint32_t* slice,
+                      hipStream_t stream)
 {
     if (n == 0)
         return JATAM_OK;
@@ -99,7 +103,7 @@ int launch_shape_hist(const jatam_result_t* recs, uint64_t n, jatam_shape_count_
     const uint64_t cap = (uint64_t)(cus > 0 ? cus : 256) * 4;
     const uint32_t blocks = (uint32_t)(want < cap ? want : cap);
     hipLaunchKernelGGL(shape_hist_kernel, dim3(blocks), dim3(kHistThreads), 0, stream, recs, n,
-                       table, log2cap, overflow);
+                       table, log2cap, overflow, slice);
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 

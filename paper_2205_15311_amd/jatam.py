@@ -112,6 +112,9 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_autotune_log.argtypes = [vp, i32, ctypes.POINTER(Tuning),
                                                ctypes.POINTER(ctypes.c_double)]
         L.jatam_batch_autotune_log.restype = i32
+        L.jatam_batch_enumerate.argtypes = [vp, u64, i64, i64, i32, i32, i32, i32, u64, vp, vp,
+                                            vp, i64, vp]
+        L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
         L.jatam_shape_histogram.restype = i32
         _lib = L
@@ -371,6 +374,28 @@ class Batch:
                                                           _stream_handle(stream))
         _check(rc, "jatam_batch_classify_items")
         return rec
+
+    def enumerate(self, first: int, slice_n: int, slices: int, t: int, c: int = 8,
+                  grid_limit: int = 16, runs: int = 20, seed: int = 1,
+                  out: torch.Tensor | None = None, tally: torch.Tensor | None = None,
+                  shapes: torch.Tensor | None = None, stream=None):
+        """jatam_batch_enumerate: `slices` graph replays of one slice's
+        pipeline over [first, first + slice_n * slices).  out: None or an
+        int32 (slice_n * slices, 4) tensor; shapes: None or a table as for
+        shape_histogram (int64 (capacity, 2))."""
+        if out is not None:
+            _records(slice_n * slices, out.device, out)
+        if shapes is not None and (shapes.dtype != torch.int64 or shapes.dim() != 2
+                                   or shapes.shape[1] != 2 or not shapes.is_cuda):
+            raise ValueError("shapes must be a device int64 tensor (capacity, 2)")
+        rc = lib().jatam_batch_enumerate(self._h, first, slice_n, slices, t, c, grid_limit, runs,
+                                         seed, out.data_ptr() if out is not None else None,
+                                         self._tally_ptr(tally),
+                                         shapes.data_ptr() if shapes is not None else None,
+                                         shapes.shape[0] if shapes is not None else 0,
+                                         _stream_handle(stream))
+        _check(rc, "jatam_batch_enumerate")
+        return out
 
     def get_tuning(self, grid_limit: int) -> dict:
         t = Tuning()

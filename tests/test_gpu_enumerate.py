@@ -1,0 +1,103 @@
+"""Graph-replayed enumeration (jatam_batch_enumerate): one captured slice
+pipeline launched once per slice.  Every replay's records, and the tally and
+shape histogram accumulated over the replays, equal the oracle's (golden
+digests or direct oracle calls).  Eager calls run between enumerations."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def jt():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    import paper_2205_15311_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+def shapes_of(jt, table):
+    return [(int(e["hash"]), int(e["size"]), int(e["count"]))
+            for e in jt.shape_table_to_numpy(table)]
+
+
+def test_s28_in_16_graph_replays(jt):
+    gold = golden("s28_digests.json")
+    n = gold["slice"]
+    out = torch.empty((16 * n, 4), dtype=torch.int32, device="cuda")
+    tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+    table = torch.zeros((256, 2), dtype=torch.int64, device="cuda")
+    with jt.Batch(n) as b:
+        b.enumerate(0, n, 16, 2, 8, 16, 20, 1, out=out, tally=tally, shapes=table)
+        torch.cuda.synchronize()
+        rec = out.cpu().numpy()
+        for s in gold["slices"]:
+            blob = rec[s["first"]:s["first"] + s["n"]].tobytes()
+            assert hashlib.sha256(blob).hexdigest() == s["sha256"], s["first"]
+        assert tally.cpu().tolist() == gold["tally"]
+        assert shapes_of(jt, table) == [(s["hash"], s["size"], s["count"]) for s in gold["shapes"]]
+
+        # eager work on the same workspace, then a second enumeration with a
+        # new capture: S_{1,8} kept only as tally and histogram
+        b.classify_range(0, 4096, 1, 8, 16, 20, 1)
+        torch.cuda.synchronize()
+        g18 = golden("s18_digests.json")
+        tally.zero_()
+        table.zero_()
+        b.enumerate(0, 1024, 4, 1, 8, 16, 20, 1, tally=tally, shapes=table)
+        torch.cuda.synchronize()
+        assert tally.cpu().tolist() == g18["tally"]
+        assert shapes_of(jt, table) == [(s["hash"], s["size"], s["count"]) for s in g18["shapes"]]
+
+
+def test_s28_tally_and_shapes_without_records(jt):
+    gold = golden("s28_digests.json")
+    tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+    table = torch.zeros((256, 2), dtype=torch.int64, device="cuda")
+    with jt.Batch(1 << 22) as b:
+        b.enumerate(0, 1 << 22, 4, 2, 8, 16, 20, 1, tally=tally, shapes=table)
+        torch.cuda.synchronize()
+    assert tally.cpu().tolist() == gold["tally"]
+    assert shapes_of(jt, table) == [(s["hash"], s["size"], s["count"]) for s in gold["shapes"]]
+
+
+def test_three_tile_g32_replays(jt):
+    first, n, k = 8_000_000_000, 1 << 16, 5
+    out = torch.empty((k * n, 4), dtype=torch.int32, device="cuda")
+    with jt.Batch(n) as b:
+        for _ in range(2):      # the same enumeration twice: replays agree with the oracle
+            out.fill_(-7)
+            b.enumerate(first, n, k, 3, 8, 32, 20, 1, out=out)
+            torch.cuda.synchronize()
+            rec = out.cpu().numpy().view(ref.RECORD).reshape(-1)
+            pick = np.sort(np.random.default_rng(2).choice(k * n, size=4096, replace=False))
+            want = ref.classify(np.uint64(first) + pick.astype(np.uint64), 3, grid=32)
+            assert np.array_equal(rec[pick], want)
+            for lo in (0, n - 512, 2 * n, k * n - 512):
+                assert np.array_equal(rec[lo:lo + 512],
+                                      ref.classify_range(first + lo, 512, 3, grid=32)), lo
+
+
+def test_enumerate_argument_errors(jt):
+    with jt.Batch(1024) as b:
+        for args in ((0, 0, 1), (0, 2048, 1), (0, 1024, 0), ((1 << 24) - 1024, 1024, 2)):
+            with pytest.raises(jt.JatamError):
+                b.enumerate(args[0], args[1], args[2], 2, 8, 16, 20, 1)
+        bad = torch.zeros((100, 2), dtype=torch.int64, device="cuda")
+        with pytest.raises(jt.JatamError):
+            b.enumerate(0, 1024, 1, 2, 8, 16, 20, 1, shapes=bad)
