@@ -107,8 +107,8 @@ struct RunState {
 //
 // Invariant: the PEND nibble of a cell is zero unless the cell is on the
 // frontier, so a new pending tile is written with one LDS atomic OR.
-template <int W, int B, int TM>
-__device__ __forceinline__ int update_site(const Model<TM>& m, LaneGrid<W, B>& g, RunState& st,
+template <int W, int B, class Src>
+__device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
                                            int G, int p, uint32_t tuple)
 {
     constexpr int kMask = W * W - 1;
@@ -118,7 +118,7 @@ __device__ __forceinline__ int update_site(const Model<TM>& m, LaneGrid<W, B>& g
     for (int d = 0; d < 4; ++d) {
         const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
         q[d] = (p + delta) & kMask;
-        opt[d] = site_options(m, tuple, d);
+        opt[d] = m.options(tuple, d);
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -177,8 +177,8 @@ struct DrawCache {
 
 // Starts a run: clears what the previous run touched, places the seed
 // (tile 0, unrotated) at the centre and checks its neighbours.
-template <int W, int B, int TM>
-__device__ __forceinline__ int run_start(const Model<TM>& m, LaneGrid<W, B>& g, RunState& st,
+template <int W, int B, class Src>
+__device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunState& st,
                                          DrawCache& dc, int G)
 {
     for (uint32_t s = st.osum; s; s &= s - 1)
@@ -201,7 +201,7 @@ __device__ __forceinline__ int run_start(const Model<TM>& m, LaneGrid<W, B>& g, 
     const int seed_pos = (G / 2 - 1) * W + (G / 2 - 1);
     g.occ(seed_pos >> 5) = 1u << (seed_pos & 31);
     st.osum = 1u << (seed_pos >> 5);
-    return update_site(m, g, st, G, seed_pos, seed_tile(m));
+    return update_site(m, g, st, G, seed_pos, m.seed());
 }
 
 // A run is over once an event happened or the frontier is empty.  Every step
@@ -214,8 +214,8 @@ __device__ __forceinline__ bool run_over(int ev, const RunState& st, int G)
 // One step: draw the frontier site of rank floor(u*|F|/2^32) in row-major
 // order (u = Philox word `steps` of this run's stream; no draw is needed with
 // one site), place its pending tile and check the new neighbours.
-template <int W, int B, int TM>
-__device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, RunState& st,
+template <int W, int B, class Src>
+__device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunState& st,
                                         DrawCache& dc, int G, int run, uint32_t key0,
                                         uint32_t key1, uint32_t rid_lo, uint32_t rid_hi)
 {
@@ -278,7 +278,7 @@ __device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, R
     const uint32_t pw = pwr;
     const uint32_t sh = ((uint32_t)p & 7u) * 4u;
     pwr = pw & ~(15u << sh);
-    const uint32_t tuple = oriented_tile(m, (int)((pw >> sh) & 15u));
+    const uint32_t tuple = m.oriented((int)((pw >> sh) & 15u));
     LaneGrid<W, B>::set_bits(g.occ(w), 1u << bit);
     st.osum |= 1u << w;
     st.size += 1;
@@ -287,8 +287,8 @@ __device__ __forceinline__ int run_step(const Model<TM>& m, LaneGrid<W, B>& g, R
 }
 
 // One run from the seed to completion or to an event.
-template <int W, int B, int TM>
-__device__ int run_assembly(const Model<TM>& m, LaneGrid<W, B>& g, RunState& st, int G, int run,
+template <int W, int B, class Src>
+__device__ int run_assembly(const Src& m, LaneGrid<W, B>& g, RunState& st, int G, int run,
                             uint32_t key0, uint32_t key1, uint32_t rid_lo, uint32_t rid_hi)
 {
     DrawCache dc;

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
     bool busy = false;
     uint32_t idx = 0;
     Geno gd{0, 0, 0, 0, false};
-    Model<TM> m;
+    ModelSource<TM> m;
     int ev = kEvNone;
 
     for (;;) {
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
                 if (rank < take) {
                     idx = ring[(head + rank) % kRing];
                     gd = fetch_geno(a, idx);
-                    m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
+                    m.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                     ev = run_start(m, g, st, dc, gd.grid);
                     busy = true;
                 }
@@ -440,7 +440,7 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
     return v;
 }
 
-template <int W, int TM>
+template <int W, int TM, bool kTable>
 __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
@@ -481,13 +481,33 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             next_idx = queue[base + stride + grp];
         Geno gd{0, 0, 0, 0, false};
         int ev = kEvNone;
-        if (active) {
-            gd = fetch_geno(a, idx);
-            const Model<TM> m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
-            ev = run_assembly(m, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
-                              (uint32_t)(gd.rng_id >> 32));
+        if constexpr (kTable) {
+            // the group builds its genotype's bond table together (word j by
+            // lane j of the group), shared through the orientation slots
+            TableSource<TM> src;
+            if (active) {
+                gd = fetch_geno(a, idx);
+                src.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
+                for (int j = run; j < 8; j += R)
+                    orient[j][grp] = bond_table_word(src.m, j);
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    src.w[j] = orient[j][grp];
+                ev = run_assembly(src, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
+                                  (uint32_t)(gd.rng_id >> 32));
+            }
+        } else {
+            if (active) {
+                gd = fetch_geno(a, idx);
+                const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
+                ev = run_assembly(src, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
+                                  (uint32_t)(gd.rng_id >> 32));
+            }
         }
-        __syncthreads();   // every run's grid is final
+        __syncthreads();   // every run's grid is final (and the table slots read)
         // a witness is a later run that hit an event or ended in another shape
         bool same = true;
         if (active && run > 0 && ev == kEvNone) {
@@ -603,7 +623,7 @@ static void occupancy_of(int out[2])
             hipSuccess ||
         out[0] < 1)
         out[0] = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[1], repeat_kernel<W, TM>, 64, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[1], repeat_kernel<W, TM, true>, 64, 0) !=
             hipSuccess ||
         out[1] < 1)
         out[1] = 1;
@@ -683,10 +703,16 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nb), dim3(256), 0, stream, a, k);
         end(kStageSort + 3 * k);
         begin(kStageRepeat + 3 * k);
-        if (k == 0)
-            hipLaunchKernelGGL((repeat_kernel<16, TM>), dim3(rb), dim3(64), 0, stream, a, 0);
+        // the bond table holds colours 0..7
+        const bool table = a.c <= 8;
+        if (k == 0 && table)
+            hipLaunchKernelGGL((repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a, 0);
+        else if (k == 0)
+            hipLaunchKernelGGL((repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a, 0);
+        else if (table)
+            hipLaunchKernelGGL((repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a, 1);
         else
-            hipLaunchKernelGGL((repeat_kernel<32, TM>), dim3(rb), dim3(64), 0, stream, a, 1);
+            hipLaunchKernelGGL((repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a, 1);
         end(kStageRepeat + 3 * k);
     }
 }

@@ -212,4 +212,53 @@ __device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tu
     return (count << 4) | id;
 }
 
+// ---------------------------------------------------------------------------
+// Sources of bond options for the assembly loop.  Both give, for a placed
+// tile's colour tuple and a direction d, the options code of site_options;
+// the seed's tuple; and the tuple of oriented tile k.
+// ---------------------------------------------------------------------------
+// Options found by the SWAR comparison on every call.
+template <int TM>
+struct ModelSource {
+    Model<TM> m;
+
+    __device__ __forceinline__ uint32_t options(uint32_t tuple, int d) const
+    {
+        return site_options(m, tuple, d);
+    }
+    __device__ __forceinline__ uint32_t seed() const { return seed_tile(m); }
+    __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
+};
+
+// Options read from the genotype's bond table (c <= 8): the code of side d
+// and shown colour x is byte x & 3 of word 2d + (x >> 2).  The table holds
+// site_options(m, x << 4d, d) for every (d, x); d must be a compile-time
+// constant at every call (the words stay in registers).
+template <int TM>
+struct TableSource {
+    Model<TM> m;
+    uint32_t w[8];
+
+    __device__ __forceinline__ uint32_t options(uint32_t tuple, int d) const
+    {
+        const uint32_t x = (tuple >> (4 * d)) & 15u;
+        const uint32_t word = (x & 4u) ? w[2 * d + 1] : w[2 * d];
+        return (word >> ((x & 3u) * 8u)) & 0x3Fu;
+    }
+    __device__ __forceinline__ uint32_t seed() const { return seed_tile(m); }
+    __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
+};
+
+// Word j (0..7) of the bond table: sides 2j.. of the table layout above.
+template <int TM>
+__device__ __forceinline__ uint32_t bond_table_word(const Model<TM>& m, int j)
+{
+    const int d = j >> 1, x0 = 4 * (j & 1);
+    uint32_t w = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        w |= site_options(m, (uint32_t)(x0 + b) << (4 * d), d) << (8 * b);
+    return w;
+}
+
 }  // namespace jatam

@@ -15,7 +15,7 @@ __device__ jatam_result_t classify_genotype(LaneGrid<W, B>& g, RunState& st, uin
                                             uint64_t rng_id, const Params& prm)
 {
     using Geo = Geometry<W>;
-    const Model<TM> m = build_model<TM>(genome, prm.t, prm.bits, prm.c);
+    const ModelSource<TM> m{build_model<TM>(genome, prm.t, prm.bits, prm.c)};
     const uint32_t rid_lo = (uint32_t)rng_id, rid_hi = (uint32_t)(rng_id >> 32);
     uint32_t occ0[Geo::kWords];
     int size0 = 0;
