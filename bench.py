@@ -145,6 +145,14 @@ def ga_report(args, jt, torch):
 
     train_s = elapsed(train_epoch)
     final_loss = float(loss.item())
+    # inference throughput of the surrogate on 4 x 65,536 candidates (the
+    # screened generation's scoring): algorithmic flops per sample = the
+    # 256 x 256 layer (2 * 256 * 256), the head (2 * 256 * 4) and the
+    # layer-1 gather (4t rows of 256 added)
+    cand = train[:4 * n].contiguous()
+    reps = 20
+    score_s = elapsed(lambda: [net.score(cand, t) for _ in range(reps)]) / reps
+    flops = 2 * 256 * 256 + 2 * 256 * 4 + 4 * t * 256
     del train, labels
 
     params = jt.GAParams(seed=5, tournament=4, mut_num=1, mut_den=12)
@@ -193,7 +201,11 @@ def ga_report(args, jt, torch):
         "data": "synthetic: uniform random three-tile population and training genotypes "
                 "(numpy Philox keys 5 and 11)",
         "surrogate": {"train_genotypes": ntrain, "train_epoch_s": train_s,
-                      "final_batch_loss": final_loss},
+                      "train_step_ms": train_s * 1e3 / (ntrain // 4096),
+                      "final_batch_loss": final_loss,
+                      "score_samples_per_s": 4 * n / score_s,
+                      "score_tflops": 4 * n * flops / score_s / 1e12,
+                      "score_frac_of_bf16_peak": 4 * n * flops / score_s / 2.5e15},
         "paths": results,
     }
     print(json.dumps(line), flush=True)

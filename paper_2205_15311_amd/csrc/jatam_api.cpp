@@ -801,7 +801,8 @@ int jatam_mlp_create(int64_t max_batch, int c, jatam_mlp_t** mlp)
               mlp_alloc(m, B * Hd * 2, (void**)&a.dh2) &&
               mlp_alloc(m, B * Hd * 2, (void**)&a.dh1) &&
               mlp_alloc(m, B * jatam::kMlpOut * 4, (void**)&a.dout) &&
-              mlp_alloc(m, B * 4, (void**)&a.loss);
+              mlp_alloc(m, B * 4, (void**)&a.loss) &&
+              mlp_alloc(m, jatam::mlp_partial_floats(B) * 4, (void**)&a.partial);
     if (!ok) {
         mlp_free(m);
         return JATAM_E_HIP;

@@ -288,7 +288,8 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
 
 // One run from the seed to completion or to an event.
 template <int W, int B, class Src>
-__device__ int run_assembly(const Src& m, LaneGrid<W, B>& g, RunState& st, int G, int run,
+__device__ __forceinline__ int run_assembly(const Src& m, LaneGrid<W, B>& g, RunState& st, int G,
+                                            int run,
                             uint32_t key0, uint32_t key1, uint32_t rid_lo, uint32_t rid_hi)
 {
     DrawCache dc;

@@ -46,7 +46,9 @@ struct Geno {
     bool valid;
 };
 
-__device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint32_t i)
+// `first`: the range mode's first genotype of this call (a.first, moved by
+// the slice counter of a replayed enumeration).
+__device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint64_t first, uint32_t i)
 {
     Geno g;
     if (a.items != nullptr) {
@@ -59,7 +61,7 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint32_t i)
         g.valid = g.t >= 1 && g.t <= 4 && gbits <= 64 && g.grid >= 8 && g.grid <= 32 &&
                   (g.grid & 1) == 0 && (gbits == 64 || (g.genome >> gbits) == 0);
     } else {
-        g.genome = a.genomes != nullptr ? a.genomes[i] : a.first + (uint64_t)i;
+        g.genome = a.genomes != nullptr ? a.genomes[i] : first + (uint64_t)i;
         g.t = a.t;
         g.grid = a.grid;
         g.rng_id = g.genome | ((uint64_t)(uint32_t)a.t << 56);
@@ -69,16 +71,19 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint32_t i)
     return g;
 }
 
-// A graph-replayed enumeration reads its slice from the device: the call
+// A graph-replayed enumeration reads its slice s from the device: the call
 // covers genotypes first + s*n .. and writes records at out + s*n if asked.
-__device__ __forceinline__ void apply_slice(BatchArgs& a)
+// (The kernel argument block is left untouched: a modified copy would live
+// in scratch memory.)
+__device__ __forceinline__ uint64_t slice_first(const BatchArgs& a)
 {
-    if (a.slice != nullptr) {
-        const uint64_t s = *a.slice;
-        a.first += s * (uint64_t)a.n;
-        if (a.out_per_slice)
-            a.out += s * (uint64_t)a.n;
-    }
+    return a.slice != nullptr ? a.first + (uint64_t)*a.slice * (uint64_t)a.n : a.first;
+}
+
+__device__ __forceinline__ jatam_result_t* slice_out(const BatchArgs& a)
+{
+    return a.slice != nullptr && a.out_per_slice ? a.out + (uint64_t)*a.slice * (uint64_t)a.n
+                                                 : a.out;
 }
 
 __global__ void slice_reset_kernel(uint32_t* counter) { counter[0] = 0; }
@@ -163,10 +168,11 @@ __device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs
 constexpr int kRing = 128;   // LDS survivor ring per wave (>= 2 chunks)
 
 template <int W, int TM>
-__global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
+__global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
-    apply_slice(a);
+    const uint64_t first = slice_first(a);
+    jatam_result_t* const out = slice_out(a);
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t ring[kRing];
     __shared__ uint4 cache_mem[kShapeCache];
@@ -211,11 +217,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
                 bool done = false, keep = false;
                 int cls = 0;
                 if (in_range) {
-                    const Geno s = fetch_geno(a, i);
+                    const Geno s = fetch_geno(a, first, i);
                     if (!s.valid) {
                         // exactly one launched pass reports an invalid item
                         if (grid_class(a, s.grid) == klass)
-                            a.out[i] = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
+                            out[i] = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
                     } else if (grid_class(a, s.grid) == klass) {
                         const Model<TM> sm = build_model<TM>(s.genome, s.t, a.bits, a.c);
                         const uint32_t seed = seed_tile(sm);
@@ -227,11 +233,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
                             bonds = bonds || opt != 0;
                         }
                         if (ambiguous) {
-                            a.out[i] = jatam_result_t{JATAM_ND_SITE, 1, 0u, 0};
+                            out[i] = jatam_result_t{JATAM_ND_SITE, 1, 0u, 0};
                             done = true;
                             cls = JATAM_ND_SITE;
                         } else if (!bonds) {
-                            a.out[i] = jatam_result_t{JATAM_DET, 1, a.ws.small_hash[0], 0};
+                            out[i] = jatam_result_t{JATAM_DET, 1, a.ws.small_hash[0], 0};
                             done = true;
                             cls = JATAM_DET;
                         } else {
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
                 const uint32_t rank = (uint32_t)__popcll(idle & lanes_below());
                 if (rank < take) {
                     idx = ring[(head + rank) % kRing];
-                    gd = fetch_geno(a, idx);
+                    gd = fetch_geno(a, first, idx);
                     m.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                     ev = run_start(m, g, st, dc, gd.grid);
                     busy = true;
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(BatchArgs a, int klass)
             rec.hash = det_hash(g, a, cache, det, st.size, gd.grid);
         if (finish) {
             if (done)
-                a.out[idx] = rec;
+                out[idx] = rec;
             busy = false;
         }
         tally.add(done, cls);
@@ -441,10 +447,11 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
 }
 
 template <int W, int TM, bool kTable>
-__global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
+__global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass)
 {
     using Geo = Geometry<W>;
-    apply_slice(a);
+    const uint64_t first = slice_first(a);
+    jatam_result_t* const out = slice_out(a);
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
     __shared__ uint32_t orient[8][64];   // per group: the 8 orientation hashes
     __shared__ uint4 cache_mem[kShapeCache];
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             // lane j of the group), shared through the orientation slots
             TableSource<TM> src;
             if (active) {
-                gd = fetch_geno(a, idx);
+                gd = fetch_geno(a, first, idx);
                 src.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                 for (int j = run; j < 8; j += R)
                     orient[j][grp] = bond_table_word(src.m, j);
@@ -494,14 +501,14 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             __syncthreads();
             if (active) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    src.w[j] = orient[j][grp];
+                for (int d = 0; d < 4; ++d)
+                    src.side[d] = ((uint64_t)orient[2 * d + 1][grp] << 32) | orient[2 * d][grp];
                 ev = run_assembly(src, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
                                   (uint32_t)(gd.rng_id >> 32));
             }
         } else {
             if (active) {
-                gd = fetch_geno(a, idx);
+                gd = fetch_geno(a, first, idx);
                 const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
                 ev = run_assembly(src, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
                                   (uint32_t)(gd.rng_id >> 32));
@@ -581,7 +588,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(BatchArgs a, int klass)
             } else {
                 rec = jatam_result_t{cls, w_size, 0u, steps};
             }
-            a.out[idx] = rec;
+            out[idx] = rec;
         }
         tally.add(done, cls);
         cache.insert(done && det && small && !hit, key, h, lane);

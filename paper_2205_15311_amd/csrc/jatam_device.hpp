@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t oaat_finish(uint32_t h)
 // Oriented tile k = 4*i + r is tile i turned clockwise by r quarter turns; it
 // is held as a 16-bit word of four nibbles, side d (N=0, E=1, S=2, W=3) in
 // bits 4d..4d+3.  For every side s the colours that all 4*TM oriented tiles
-// show on s are packed as nibble k of side_cols[s], so one SWAR comparison
+// show on s are packed as nibble k of side_col(s), so one SWAR comparison
 // finds every oriented tile that shows a given colour there.  `reps` has bit
 // 4k+3 set for each k that is the first oriented tile with its colour tuple:
 // duplicates and symmetric orientations collapse onto that representative.
@@ -87,9 +87,16 @@ struct Model {
     static constexpr Word kLow3 = (Word)0x7777777777777777ull;
 
     Word tiles;          // tile i in bits 16i..16i+15, nibble d = colour of side d
-    Word side_cols[4];   // nibble k = colour oriented tile k shows on side s
+    // nibble k = colour oriented tile k shows on side s; four scalars rather
+    // than an array, so that a side chosen at run time stays in registers
+    Word cols0, cols1, cols2, cols3;
     Word reps;           // bit 4k+3 set for representative oriented tiles
     int c;               // colour count
+
+    __device__ __forceinline__ Word side_col(int s) const
+    {
+        return s == 0 ? cols0 : s == 1 ? cols1 : s == 2 ? cols2 : cols3;
+    }
 };
 
 __device__ __forceinline__ uint32_t rotate_tile(uint32_t tile, int r)
@@ -137,7 +144,14 @@ __device__ __forceinline__ Model<TM> build_model(uint64_t genome, int t, int bit
 #pragma unroll
         for (int i = 0; i < TM; ++i)
             col |= (Word)rotate_tile(reverse_nibbles16(tile[i]), (s + 1) & 3) << (16 * i);
-        m.side_cols[s] = col;
+        if (s == 0)
+            m.cols0 = col;
+        else if (s == 1)
+            m.cols1 = col;
+        else if (s == 2)
+            m.cols2 = col;
+        else
+            m.cols3 = col;
     }
     // representatives: the first orientation of each distinct colour tuple.
     // Rotation r of a tile repeats rotation 0 iff the tile has r-fold symmetry;
@@ -197,7 +211,7 @@ __device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tu
     const int p = ((x + 1) ^ 1) - 1;
     if (p < 0 || p >= m.c)
         return 0;
-    const Word v = m.side_cols[(d + 2) & 3] ^ (M::kOnes * (Word)p);
+    const Word v = m.side_col((d + 2) & 3) ^ (M::kOnes * (Word)p);
     // high bit of each nibble set iff the nibble is nonzero (no carries escape)
     const Word nonzero = v | ((v & M::kLow3) + M::kLow3);
     const Word match = ~nonzero & m.reps;
@@ -230,26 +244,26 @@ struct ModelSource {
     __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
 };
 
-// Options read from the genotype's bond table (c <= 8): the code of side d
-// and shown colour x is byte x & 3 of word 2d + (x >> 2).  The table holds
-// site_options(m, x << 4d, d) for every (d, x); d must be a compile-time
-// constant at every call (the words stay in registers).
+// Options read from the genotype's bond table (c <= 8): byte x of side[d]
+// is site_options(m, x << 4d, d), the code of shown colour x on side d.  d
+// is a compile-time constant at every call and x only selects a shift, so
+// the table stays in registers (a run-time index into an array, or a choice
+// between two of its elements, would put it in scratch memory).
 template <int TM>
 struct TableSource {
     Model<TM> m;
-    uint32_t w[8];
+    uint64_t side[4];
 
     __device__ __forceinline__ uint32_t options(uint32_t tuple, int d) const
     {
-        const uint32_t x = (tuple >> (4 * d)) & 15u;
-        const uint32_t word = (x & 4u) ? w[2 * d + 1] : w[2 * d];
-        return (word >> ((x & 3u) * 8u)) & 0x3Fu;
+        const uint32_t x = (tuple >> (4 * d)) & 7u;
+        return (uint32_t)(side[d] >> (8u * x)) & 0x3Fu;
     }
     __device__ __forceinline__ uint32_t seed() const { return seed_tile(m); }
     __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
 };
 
-// Word j (0..7) of the bond table: sides 2j.. of the table layout above.
+// Word j (0..7) of the bond table: the low (j even) or high half of side[j / 2].
 template <int TM>
 __device__ __forceinline__ uint32_t bond_table_word(const Model<TM>& m, int j)
 {

@@ -150,9 +150,12 @@ struct MlpArgs {
     uint16_t* dh1;       // [batch][256] bf16
     float* dout;         // [batch][4]
     float* loss;         // [batch] per-sample loss
+    float* partial;      // partial sums of the backward reductions
     int c, bits;
 };
 
+// Floats of MlpArgs::partial for batches of up to max_batch samples.
+size_t mlp_partial_floats(size_t max_batch);
 int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s);
 int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
                      uint32_t n, uint32_t n_pad, float* scores, hipStream_t s);

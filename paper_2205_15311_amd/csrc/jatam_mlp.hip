@@ -108,47 +108,121 @@ struct GemmArgs {
     uint16_t* C16;           // kEpBiasRelu / kEpReluMask: bf16 C[m * N + n]
     const float* bias;       // kEpBiasRelu: bias[n]
     const uint16_t* mask;    // kEpReluMask: keep where mask[m * N + n] > 0
+    int splits;              // K split across this many workgroups (kEpStoreF32 only)
+    float* partial;          // splits > 1: [splits][M][N] fp32 partial sums
 };
 
 __device__ __forceinline__ int lane16() { return (int)(__lane_id() & 15); }
 __device__ __forceinline__ int quad() { return (int)(__lane_id() >> 4); }
 
+// Block tile of the GEMM: 64 x 64 outputs per workgroup of 4 waves, each
+// wave a 32 x 32 quarter (2 x 2 MFMA tiles), K in steps of 32.  Both operand
+// tiles are staged in LDS with k contiguous, so every MFMA fragment is one
+// 16-byte LDS read; the global loads are 16 bytes along whichever of the two
+// dimensions is contiguous in memory (a transposed operand is scattered into
+// LDS).  With splits > 1 the K range is split across workgroups and each
+// writes fp32 partial sums, added in split order by mlp_reduce_kernel.
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPitch = kBK + 8;
+
+// One 64 x 32 operand tile into LDS (rows r0.., k k0..): element (r, k) of
+// the operand is src[r * s_row + k * s_k]; rows >= R are zero.  Needs R a
+// multiple of 8 and, for s_k != 1, s_row == 1.
+__device__ __forceinline__ void load_tile(const uint16_t* __restrict__ src, int64_t s_row,
+                                          int64_t s_k, int r0, int k0, int R,
+                                          uint16_t (*dst)[kLdsPitch])
+{
+    const int tid = (int)threadIdx.x;
+    if (s_k == 1) {
+        const int r = tid >> 2, kc = (tid & 3) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + r < R)
+            v = *reinterpret_cast<const uint4*>(src + (int64_t)(r0 + r) * s_row + k0 + kc);
+        *reinterpret_cast<uint4*>(&dst[r][kc]) = v;
+    } else {
+        const int k = tid >> 3, rc = (tid & 7) * 8;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r0 + rc < R)
+            v = *reinterpret_cast<const uint4*>(src + (int64_t)(k0 + k) * s_k + r0 + rc);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            dst[rc + e][k] = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+    }
+}
+
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
 {
-    const int wave = (int)(threadIdx.x >> 6);
-    const int tiles_n = g.N / 16;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= (g.M / 16) * tiles_n)
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kLdsPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kLdsPitch];
+    const int wave = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
+    const int tiles_n = (g.N + kBN - 1) / kBN;
+    const int m0 = ((int)blockIdx.x / tiles_n) * kBM, n0 = ((int)blockIdx.x % tiles_n) * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int split = (int)blockIdx.y;
+    const int kper = ((g.K / kBK + g.splits - 1) / g.splits) * kBK;
+    const int kbeg = split * kper, kend = min(g.K, kbeg + kper);
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+        load_tile(g.A, g.sam, g.sak, m0, k0, g.M, As);
+        load_tile(g.B, g.sbn, g.sbk, n0, k0, g.N, Bs);
+        __syncthreads();
+        bf16x8 af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + (l & 15)][8 * (l >> 4)]);
+            bf[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * i + (l & 15)][8 * (l >> 4)]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0,
+                                                                     0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wm + 16 * i + 4 * (l >> 4) + e;
+                const int n = n0 + wn + 16 * j + (l & 15);
+                if (m >= g.M || n >= g.N)
+                    continue;
+                const float v = acc[i][j][e];
+                const int64_t o = (int64_t)m * g.N + n;
+                if (g.splits > 1) {
+                    g.partial[(int64_t)split * g.M * g.N + o] = v;
+                } else if (g.epilogue == kEpStoreF32) {
+                    g.C32[o] = v;
+                } else if (g.epilogue == kEpBiasRelu) {
+                    const float z = v + g.bias[n];
+                    g.C16[o] = bf16_bits(z > 0.f ? z : 0.f);
+                } else {
+                    g.C16[o] = bf16_bits(g.mask[o] != 0 ? v : 0.f);
+                }
+            }
+        }
+    }
+}
+
+// out[i] = sum over s < parts of partial[s * count + i], in that order.
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float* __restrict__ partial,
+                                                         int parts, int64_t count, float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count)
         return;
-    const int m0 = (tile / tiles_n) * 16, n0 = (tile % tiles_n) * 16;
-    const int r = lane16(), q = quad();
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
-        bf16x8 av, bv;
-        const int kq = k0 + 8 * q;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const uint16_t ab = g.A[(int64_t)(m0 + r) * g.sam + (int64_t)(kq + i) * g.sak];
-            const uint16_t bb = g.B[(int64_t)(kq + i) * g.sbk + (int64_t)(n0 + r) * g.sbn];
-            av[i] = __builtin_bit_cast(__bf16, ab);
-            bv[i] = __builtin_bit_cast(__bf16, bb);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + 4 * q + i, n = n0 + r;
-        const float v = acc[i];
-        const int64_t o = (int64_t)m * g.N + n;
-        if (g.epilogue == kEpStoreF32) {
-            g.C32[o] = v;
-        } else if (g.epilogue == kEpBiasRelu) {
-            const float z = v + g.bias[n];
-            g.C16[o] = bf16_bits(z > 0.f ? z : 0.f);
-        } else {
-            g.C16[o] = bf16_bits(g.mask[o] != 0 ? v : 0.f);
-        }
-    }
+    float s = 0.f;
+    for (int p = 0; p < parts; ++p)
+        s += partial[(int64_t)p * count + i];
+    out[i] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -219,49 +293,68 @@ __global__ __launch_bounds__(256) void mlp_dh2_kernel(MlpArgs a, uint32_t n)
     a.dh2[o] = bf16_bits(a.h2[o] != 0 ? v : 0.f);
 }
 
-// Column sums: out[j] = sum_b src[b][j] (bf16 or fp32 rows), deterministic.
+// Row chunks of the batch reductions below: each block sums one chunk of
+// rows into partial[chunk][...]; mlp_reduce_kernel adds the chunks in order.
+constexpr int kRedRows = 128;
+
+// Column sums of [n][cols] rows (bf16 or fp32): partial[chunk][j].
 __global__ __launch_bounds__(256) void mlp_colsum_kernel(const uint16_t* src16, const float* src32,
-                                                         uint32_t n, int cols, float* out)
+                                                         uint32_t n, int cols, float* partial)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= cols)
-        return;
-    float s = 0.f;
-    for (uint32_t b = 0; b < n; ++b)
-        s += src16 != nullptr ? bf16_float(src16[(size_t)b * cols + j])
-                              : src32[(size_t)b * cols + j];
-    out[j] = s;
+    const uint32_t b0 = blockIdx.y * kRedRows, b1 = min(n, b0 + kRedRows);
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < cols; j += gridDim.x * 256) {
+        float s = 0.f;
+        for (uint32_t b = b0; b < b1; ++b)
+            s += src16 != nullptr ? bf16_float(src16[(size_t)b * cols + j])
+                                  : src32[(size_t)b * cols + j];
+        partial[(size_t)blockIdx.y * cols + j] = s;
+    }
 }
 
-// dW3[j][k] = sum_b h2[b][j] dout[b][k].
-__global__ __launch_bounds__(256) void mlp_dw3_kernel(MlpArgs a, uint32_t n)
+// dW3[j][k] = sum_b h2[b][j] dout[b][k]: partial[chunk][j * 4 + k].
+__global__ __launch_bounds__(256) void mlp_dw3_kernel(MlpArgs a, uint32_t n, float* partial)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= kMlpHidden * kMlpOut)
-        return;
-    const int j = idx / kMlpOut, k = idx % kMlpOut;
-    float s = 0.f;
-    for (uint32_t b = 0; b < n; ++b)
-        s = fmaf(bf16_float(a.h2[(size_t)b * kMlpHidden + j]), a.dout[(size_t)b * kMlpOut + k], s);
-    a.g.w3[idx] = s;
+    const int j = threadIdx.x;
+    const uint32_t b0 = blockIdx.x * kRedRows, b1 = min(n, b0 + kRedRows);
+    float s[kMlpOut] = {0.f, 0.f, 0.f, 0.f};
+    for (uint32_t b = b0; b < b1; ++b) {
+        const float h = bf16_float(a.h2[(size_t)b * kMlpHidden + j]);
+#pragma unroll
+        for (int k = 0; k < kMlpOut; ++k)
+            s[k] = fmaf(h, a.dout[(size_t)b * kMlpOut + k], s[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kMlpOut; ++k)
+        partial[(size_t)blockIdx.x * kMlpHidden * kMlpOut + j * kMlpOut + k] = s[k];
 }
 
-// Mean loss of the batch (one block, fixed order).
-__global__ __launch_bounds__(256) void mlp_loss_kernel(MlpArgs a, uint32_t n, float* loss_out)
+// Per-chunk loss sums: partial[chunk].
+__global__ __launch_bounds__(256) void mlp_loss_kernel(MlpArgs a, uint32_t n, float* partial)
 {
     __shared__ float part[256];
-    float s = 0.f;
-    for (uint32_t b = threadIdx.x; b < n; b += 256)
-        s += a.loss[b];
-    part[threadIdx.x] = s;
+    const uint32_t b0 = blockIdx.x * kRedRows, b1 = min(n, b0 + kRedRows);
+    const uint32_t b = b0 + threadIdx.x;
+    part[threadIdx.x] = b < b1 ? a.loss[b] : 0.f;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off)
             part[threadIdx.x] += part[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss_out != nullptr)
-        loss_out[0] = part[0] / (float)n;
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = part[0];
+}
+
+// loss_out = (sum of the chunk sums) / n.
+__global__ void mlp_loss_final_kernel(const float* partial, int chunks, uint32_t n,
+                                      float* loss_out)
+{
+    if (threadIdx.x != 0)
+        return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c)
+        s += partial[c];
+    loss_out[0] = s / (float)n;
 }
 
 // Adam on the flat fp32 parameter vector; refreshes the bf16 weight copies.
@@ -318,11 +411,40 @@ __global__ __launch_bounds__(256) void mlp_init_kernel(MlpArgs a, uint32_t k0, u
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-static int gemm(const GemmArgs& g, hipStream_t s)
+// C = A B (M x N, K a multiple of 32, M and N multiples of 8).  Store
+// epilogues with a long K are split across workgroups (fp32 partials in
+// `partial`, added in split order).
+static int gemm(GemmArgs g, float* partial, hipStream_t s)
 {
-    const int tiles = (g.M / 16) * (g.N / 16);
-    hipLaunchKernelGGL(mlp_gemm_kernel, dim3((tiles + 3) / 4), dim3(256), 0, s, g);
+    const int tiles = ((g.M + kBM - 1) / kBM) * ((g.N + kBN - 1) / kBN);
+    g.splits = 1;
+    if (g.epilogue == kEpStoreF32) {
+        const int want = g.K / 256;
+        g.splits = want < 1 ? 1 : want > 16 ? 16 : want;
+    }
+    g.partial = partial;
+    hipLaunchKernelGGL(mlp_gemm_kernel, dim3(tiles, g.splits), dim3(256), 0, s, g);
+    if (g.splits > 1) {
+        const int64_t count = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                           s, (const float*)partial, g.splits, count, g.C32);
+    }
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
+size_t mlp_partial_floats(size_t max_batch)
+{
+    const size_t chunks = (max_batch + kRedRows - 1) / kRedRows;
+    const size_t split = (size_t)16 * kMlpHidden * kMlpHidden;       // dW2, 16 splits
+    const size_t rows = chunks * (size_t)(kMlpHidden * kMlpOut);      // dW3 chunk sums
+    return split > rows ? split : rows;
+}
+
+// Sum of `chunks` partial rows of `cols` floats into out (fixed order).
+static void reduce_rows(const float* partial, int chunks, int cols, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s,
+                       partial, chunks, (int64_t)cols, out);
 }
 
 int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s)
@@ -360,7 +482,7 @@ int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t*
     g.epilogue = kEpBiasRelu;
     g.C16 = a.h2;
     g.bias = a.p.b2;
-    int rc = gemm(g, s);
+    int rc = gemm(g, a.partial, s);
     if (rc != JATAM_OK)
         return rc;
     hipLaunchKernelGGL(mlp_head_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n, labels,
@@ -387,7 +509,7 @@ int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* t
     g.epilogue = kEpBiasRelu;
     g.C16 = a.h2;
     g.bias = a.p.b2;
-    int rc = gemm(g, s);
+    int rc = gemm(g, a.partial, s);
     if (rc != JATAM_OK)
         return rc;
     hipLaunchKernelGGL(mlp_head_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n,
@@ -399,11 +521,18 @@ int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* t
 int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* loss_out,
                         hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_loss_kernel, dim3(1), dim3(256), 0, s, a, n, loss_out);
-    hipLaunchKernelGGL(mlp_dw3_kernel, dim3((kMlpHidden * kMlpOut + 255) / 256), dim3(256), 0, s,
-                       a, n);
-    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)nullptr,
-                       (const float*)a.dout, n, kMlpOut, a.g.b3);
+    const int chunks = (int)((n + kRedRows - 1) / kRedRows);
+    const int chunks_pad = (int)((n_pad + kRedRows - 1) / kRedRows);
+    if (loss_out != nullptr) {
+        hipLaunchKernelGGL(mlp_loss_kernel, dim3(chunks), dim3(256), 0, s, a, n, a.partial);
+        hipLaunchKernelGGL(mlp_loss_final_kernel, dim3(1), dim3(64), 0, s, (const float*)a.partial,
+                           chunks, n, loss_out);
+    }
+    hipLaunchKernelGGL(mlp_dw3_kernel, dim3(chunks), dim3(kMlpHidden), 0, s, a, n, a.partial);
+    reduce_rows(a.partial, chunks, kMlpHidden * kMlpOut, a.g.w3, s);
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1, chunks), dim3(256), 0, s,
+                       (const uint16_t*)nullptr, (const float*)a.dout, n, kMlpOut, a.partial);
+    reduce_rows(a.partial, chunks, kMlpOut, a.g.b3, s);
     hipLaunchKernelGGL(mlp_dh2_kernel, dim3(n_pad), dim3(256), 0, s, a, n);
     // dW2 = h1^T dh2 (M = K_hidden rows of h1^T, K = batch)
     GemmArgs g{};
@@ -418,11 +547,13 @@ int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* los
     g.K = (int)n_pad;
     g.epilogue = kEpStoreF32;
     g.C32 = a.g.w2;
-    int rc = gemm(g, s);
+    int rc = gemm(g, a.partial, s);
     if (rc != JATAM_OK)
         return rc;
-    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)a.dh2,
-                       (const float*)nullptr, n_pad, kMlpHidden, a.g.b2);
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1, chunks_pad), dim3(256), 0, s,
+                       (const uint16_t*)a.dh2, (const float*)nullptr, n_pad, kMlpHidden,
+                       a.partial);
+    reduce_rows(a.partial, chunks_pad, kMlpHidden, a.g.b2, s);
     // dh1 = bf16((dh2 W2^T) * (h1 > 0))
     g = GemmArgs{};
     g.A = a.dh2;
@@ -437,10 +568,12 @@ int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* los
     g.epilogue = kEpReluMask;
     g.C16 = a.dh1;
     g.mask = a.h1;
-    if ((rc = gemm(g, s)) != JATAM_OK)
+    if ((rc = gemm(g, a.partial, s)) != JATAM_OK)
         return rc;
-    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1), dim3(256), 0, s, (const uint16_t*)a.dh1,
-                       (const float*)nullptr, n_pad, kMlpHidden, a.g.b1);
+    hipLaunchKernelGGL(mlp_colsum_kernel, dim3(1, chunks_pad), dim3(256), 0, s,
+                       (const uint16_t*)a.dh1, (const float*)nullptr, n_pad, kMlpHidden,
+                       a.partial);
+    reduce_rows(a.partial, chunks_pad, kMlpHidden, a.g.b1, s);
     // dW1 = x^T dh1
     g = GemmArgs{};
     g.A = a.x;
@@ -454,7 +587,7 @@ int mlp_launch_backward(const MlpArgs& a, uint32_t n, uint32_t n_pad, float* los
     g.K = (int)n_pad;
     g.epilogue = kEpStoreF32;
     g.C32 = a.g.w1;
-    return gemm(g, s);
+    return gemm(g, a.partial, s);
 }
 
 int mlp_launch_adam(const MlpArgs& a, float lr, int step, hipStream_t s)
