@@ -364,7 +364,10 @@ int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_
                          void* stream);
 
 /* Screening score of each genome: P(DET) * exp(predicted log1p size) - 1,
- * the expected size of a deterministic structure (device float [n]). */
+ * the expected size of a deterministic structure (device float [n]).  One
+ * fused pass (layer-1 gather, h1 W2 and the head on the matrix cores, 64
+ * genomes per workgroup); n is not limited by max_batch and no activations
+ * are kept. */
 int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
                     int64_t n, float* scores, void* stream);
 

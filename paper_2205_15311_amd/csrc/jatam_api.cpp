@@ -736,7 +736,7 @@ struct jatam_mlp {
     int64_t max_batch;     // padded to a multiple of 32
     int step;              // Adam steps taken since the parameters were set
     jatam::MlpArgs a;
-    void* allocations[16];
+    void* allocations[24];
     int nalloc;
 };
 
@@ -796,6 +796,8 @@ int jatam_mlp_create(int64_t max_batch, int c, jatam_mlp_t** mlp)
               mlp_alloc(m, (size_t)jatam::kMlpIn * Hd * 2, (void**)&a.w1b) &&
               mlp_alloc(m, Hd * Hd * 2, (void**)&a.w2b) &&
               mlp_alloc(m, Hd * jatam::kMlpOut * 2, (void**)&a.w3b) &&
+              mlp_alloc(m, Hd * Hd * 2, (void**)&a.w2t) &&
+              mlp_alloc(m, 16 * Hd * 2, (void**)&a.w3t) &&
               mlp_alloc(m, B * jatam::kMlpIn * 2, (void**)&a.x) &&
               mlp_alloc(m, B * Hd * 2, (void**)&a.h1) && mlp_alloc(m, B * Hd * 2, (void**)&a.h2) &&
               mlp_alloc(m, B * Hd * 2, (void**)&a.dh2) &&
@@ -811,7 +813,9 @@ int jatam_mlp_create(int64_t max_batch, int c, jatam_mlp_t** mlp)
     mlp_views(g, &a.g);
     a.c = c;
     a.bits = bits;
-    if (jatam::mlp_launch_init(a, 0x5eed, nullptr) != JATAM_OK ||
+    // the padding rows of the transposed head weights stay zero
+    if (hipMemset(a.w3t, 0, 16 * Hd * 2) != hipSuccess ||
+        jatam::mlp_launch_init(a, 0x5eed, nullptr) != JATAM_OK ||
         hipDeviceSynchronize() != hipSuccess) {
         mlp_free(m);
         return JATAM_E_HIP;
@@ -909,10 +913,11 @@ int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t,
         (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
         return JATAM_E_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
-    for (int64_t at = 0; at < n; at += mlp->max_batch) {
-        const int64_t k = n - at < mlp->max_batch ? n - at : mlp->max_batch;
+    // one fused pass, in pieces of at most 2^31 samples (no activations kept)
+    for (int64_t at = 0; at < n; at += (int64_t)1 << 31) {
+        const int64_t k = n - at < ((int64_t)1 << 31) ? n - at : ((int64_t)1 << 31);
         const int rc = jatam::mlp_launch_score(mlp->a, genomes + at, t ? t + at : nullptr, t_all,
-                                               (uint32_t)k, pad32(k), scores + at, s);
+                                               (uint32_t)k, scores + at, s);
         if (rc != JATAM_OK)
             return rc;
     }

@@ -143,6 +143,8 @@ struct MlpArgs {
     uint16_t* w1b;       // bf16 copies of the weights
     uint16_t* w2b;
     uint16_t* w3b;
+    uint16_t* w2t;       // [256][256] bf16 W2 transposed (k contiguous)
+    uint16_t* w3t;       // [16][256] bf16 W3 transposed, rows 4..15 zero
     uint16_t* x;         // [batch][96] one-hot inputs (bf16)
     uint16_t* h1;        // [batch][256] bf16
     uint16_t* h2;        // [batch][256] bf16
@@ -158,7 +160,7 @@ struct MlpArgs {
 size_t mlp_partial_floats(size_t max_batch);
 int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s);
 int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
-                     uint32_t n, uint32_t n_pad, float* scores, hipStream_t s);
+                     uint32_t n, float* scores, hipStream_t s);
 int mlp_launch_refresh(const MlpArgs& a, hipStream_t s);
 int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
                        uint32_t n, uint32_t n_pad, const jatam_result_t* labels, float* out4,
