@@ -52,16 +52,23 @@ def algorithmic_ops(n, steps, det_count, det_size):
     return OPS_GENOTYPE * n + OPS_PLACEMENT * steps + hash_ops(det_count, det_size)
 
 
+OPS_PROOF_CELL = 100.0   # forced-shape check: four neighbour lookups per cell
+
+
 def stage_ops(gold):
     """The same work split over the pipeline's kernels (per whole-space call):
-    first runs (with the seed screen) and the repeat runs of candidates."""
+    first runs (with the seed screen); the replayed first runs of the
+    candidates and the forced-shape check (forced candidates are final
+    there); the repeat runs of the other candidates."""
     w = gold["work"]
     return {
         "first_run_kernel<16>": OPS_GENOTYPE * gold["total"]
         + hash_ops(w["monomer_det"], w["monomer_det"])
         + OPS_PLACEMENT * w["run0_steps"] + hash_ops(w["run0_det"], w["run0_det_size"]),
-        "repeat_kernel<16>": OPS_PLACEMENT * w["repeat_steps"]
-        + hash_ops(w["repeat_det"], w["repeat_det_size"]),
+        "prove_kernel<16>": OPS_PLACEMENT * w["cand_steps0"] + OPS_PROOF_CELL * w["cand_size"]
+        + hash_ops(w["forced"], w["forced_size"]),
+        "repeat_kernel<16>": OPS_PLACEMENT * w["unproven_steps"]
+        + hash_ops(w["unproven_det"], w["unproven_det_size"]),
     }
 
 

@@ -267,8 +267,8 @@ int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* 
  * calls and writes, per stage s < max_stages, the summed duration in ms over
  * those calls to ms[s] and, if calls is not NULL, how many calls ran it to
  * calls[s]; it returns the number of stages written.  Stage names:
- * jatam_batch_stage_name (0 first runs, 1 size sort, 2 repeat runs for
- * G <= 16; 3-5 the same for G <= 32).
+ * jatam_batch_stage_name (0 first runs, 1 size sort, 2 forced-shape proof
+ * and compaction, 3 repeat runs for G <= 16; 4-7 the same for G <= 32).
  */
 int jatam_batch_set_timing(jatam_batch_t* batch, int enable);
 int jatam_batch_stage_times(jatam_batch_t* batch, double* ms, int* calls, int max_stages);

@@ -408,7 +408,40 @@ typedef struct {
     int steps;
     int event;
     int choice;
+    int forced;     /* the first run's shape is forced (forced_shape) */
 } run0_info_t;
+
+/* Whether the shape the run left in g is forced: for every occupied cell
+ * and every occupied neighbour, the tiles that bond to the neighbour's tile
+ * on the side facing the cell are none, or exactly the cell's own tile.  A
+ * cell's options in any growth order are the union of such sets over the
+ * neighbours present at the time, so every order then places the same tile
+ * in every cell of the shape, and never meets two options.  (Sites outside
+ * the shape that a shape tile bonds to cannot exist after a run that ended
+ * with an empty frontier and no event.) */
+static int forced_shape(const model_t* m, const grid_t* g)
+{
+    for (int p = 0; p < g->W * g->W; ++p) {
+        if (g->cell[p] < 0)
+            continue;
+        int px = p % g->W, py = p / g->W;
+        for (int d = 0; d < 4; ++d) {
+            int qx = px + DX[d], qy = py + DY[d];
+            if (qx < 0 || qy < 0 || qx >= g->W || qy >= g->W)
+                continue;
+            int q = qy * g->W + qx;
+            if (g->cell[q] < 0)
+                continue;
+            /* the neighbour shows this colour towards p; p's tile faces
+             * back on side d */
+            int id = -1;
+            int k = options(m, m->tup[g->cell[q]][opposite(d)], d, &id);
+            if (k >= 2 || (k == 1 && id != g->cell[p]))
+                return 0;
+        }
+    }
+    return 1;
+}
 
 static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome,
                          uint64_t rng_id, int t, int c, int grid, int runs,
@@ -430,6 +463,7 @@ static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome
             info0->steps = ro.steps;
             info0->event = ro.event;
             info0->choice = ro.choice;
+            info0->forced = ro.event == EV_NONE && forced_shape(&m, g);
         }
         if (ro.event != EV_NONE) {
             out->cls = ro.event == EV_UNBOUND ? JREF_UNBOUND : JREF_ND_SITE;
@@ -525,6 +559,7 @@ typedef struct {
     int32_t* run0_steps;   /* optional run-0 detail          */
     int8_t* run0_event;
     int8_t* run0_choice;
+    int8_t* run0_forced;
     int64_t next;          /* next unclaimed index (atomic)  */
     int error;             /* first error seen (atomic)      */
 } job_t;
@@ -554,7 +589,7 @@ static void* worker(void* arg)
             } else {
                 uint64_t g = job->mode == MODE_RANGE ? job->first + (uint64_t)i
                                                      : job->genomes[i];
-                run0_info_t info = { 0, 0, 0 };
+                run0_info_t info = { 0, 0, 0, 0 };
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, g,
                                    jref_default_rng_id(g, job->t), job->t, job->c,
                                    job->grid, job->runs, job->seed, &job->out[i], NULL,
@@ -563,6 +598,7 @@ static void* worker(void* arg)
                     job->run0_steps[i] = info.steps;
                     job->run0_event[i] = (int8_t)info.event;
                     job->run0_choice[i] = (int8_t)info.choice;
+                    job->run0_forced[i] = (int8_t)info.forced;
                 }
             }
             if (rc != JREF_OK)
@@ -602,7 +638,7 @@ int jref_classify(const uint64_t* genomes, int64_t n, int t, int c, int grid,
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_LIST, genomes, NULL, 0, n, t, c, grid, runs, seed, out,
-                  NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -612,20 +648,20 @@ int jref_classify_range(uint64_t first, int64_t n, int t, int c, int grid,
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
-                  NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }
 
 int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
                              int runs, uint64_t seed, jref_result_t* out,
                              int32_t* run0_steps, int8_t* run0_event,
-                             int8_t* run0_choice, int threads)
+                             int8_t* run0_choice, int8_t* run0_forced, int threads)
 {
     if (jref_check_args(t, c, grid, runs) != JREF_OK || !run0_steps || !run0_event ||
-        !run0_choice)
+        !run0_choice || !run0_forced)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
-                  run0_steps, run0_event, run0_choice, 0, 0 };
+                  run0_steps, run0_event, run0_choice, run0_forced, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -635,6 +671,6 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
     if (jref_check_args(1, c, 16, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_ITEMS, NULL, items, 0, n, 1, c, 16, runs, seed, out,
-                  NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }

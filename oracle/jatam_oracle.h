@@ -105,7 +105,7 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
 int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
                              int runs, uint64_t seed, jref_result_t* out,
                              int32_t* run0_steps, int8_t* run0_event,
-                             int8_t* run0_choice, int threads);
+                             int8_t* run0_choice, int8_t* run0_forced, int threads);
 
 /* Traces one run: writes the placed cells in placement order (y*(G+1)+x,
  * seed first) to cells_out (capacity cap) and returns the event code of the

@@ -63,7 +63,8 @@ def lib() -> ctypes.CDLL:
         L.jref_classify_range_run0.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
                                                ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
-                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int]
         L.jref_classify_range_run0.restype = ctypes.c_int
         L.jref_ga_offspring.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -145,17 +146,20 @@ def classify_range(first: int, n: int, t: int, c: int = 8, grid: int = 16, runs:
 
 
 def classify_range_run0(first: int, n: int, t: int, c: int = 8, grid: int = 16,
-                        runs: int = 20, seed: int = 1, threads: int = 0):
-    """Records plus (steps, event, choice) of every genotype's first run."""
+                        runs: int = 20, seed: int = 1, threads: int = 0, forced: bool = False):
+    """Records plus (steps, event, choice) of every genotype's first run, and
+    with forced=True also whether the first run's shape is forced."""
     out = np.zeros(n, dtype=RECORD)
     s0 = np.zeros(n, dtype=np.int32)
     e0 = np.zeros(n, dtype=np.int8)
     c0 = np.zeros(n, dtype=np.int8)
+    f0 = np.zeros(n, dtype=np.int8)
     rc = lib().jref_classify_range_run0(first, n, t, c, grid, runs, seed, out.ctypes.data,
-                                        s0.ctypes.data, e0.ctypes.data, c0.ctypes.data, threads)
+                                        s0.ctypes.data, e0.ctypes.data, c0.ctypes.data,
+                                        f0.ctypes.data, threads)
     if rc != 0:
         raise ValueError(f"oracle rejected arguments (rc={rc})")
-    return out, s0, e0, c0
+    return (out, s0, e0, c0, f0) if forced else (out, s0, e0, c0)
 
 
 def classify_items(items: np.ndarray, c: int = 8, runs: int = 20, seed: int = 1,

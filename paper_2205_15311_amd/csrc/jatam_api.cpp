@@ -17,7 +17,7 @@ struct jatam_batch {
     jatam_tuning_t tune[2];        // launch parameters per grid class
     std::vector<std::pair<jatam_tuning_t, double>> tune_log;   // last autotune
     jatam::DeviceWorkspace ws;
-    void* allocations[20];
+    void* allocations[24];
     int nalloc;
     // graph of the last enumeration (kept until the next one or destroy)
     hipStream_t capture_stream;
@@ -270,6 +270,9 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
                          (void**)&ws.seg_hist[k]) &&
              batch_alloc(b, (size_t)jatam::kMaxScanBlocks * sizeof(uint32_t),
                          (void**)&ws.scan_sums[k]) &&
+             batch_alloc(b, (n / 64 + 1) * sizeof(uint32_t), (void**)&ws.chunk_cnt[k]) &&
+             batch_alloc(b, (n / 64 / jatam::kScanBlock + 1) * sizeof(uint32_t),
+                         (void**)&ws.chunk_sums[k]) &&
              batch_alloc(b, staging * sizeof(uint32_t), (void**)&ws.cand_idx[k]) &&
              batch_alloc(b, staging * sizeof(uint16_t), (void**)&ws.cand_size[k]) &&
              batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.sorted[k]);
@@ -663,8 +666,8 @@ int jatam_batch_stage_times(jatam_batch_t* batch, double* ms, int* calls, int ma
 const char* jatam_batch_stage_name(int stage)
 {
     static const char* names[jatam::kStages] = {
-        "first_run_kernel<16>", "size_sort<16>", "repeat_kernel<16>",
-        "first_run_kernel<32>", "size_sort<32>", "repeat_kernel<32>"};
+        "first_run_kernel<16>", "size_sort<16>", "prove_kernel<16>", "repeat_kernel<16>",
+        "first_run_kernel<32>", "size_sort<32>", "prove_kernel<32>", "repeat_kernel<32>"};
     return stage >= 0 && stage < jatam::kStages ? names[stage] : "";
 }
 

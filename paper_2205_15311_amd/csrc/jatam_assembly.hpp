@@ -105,8 +105,9 @@ struct RunState {
 // one admissible tile joins the frontier with that tile pending.  All reads
 // of the four neighbours are issued before any of them is used.
 //
-// Invariant: the PEND nibble of a cell is zero unless the cell is on the
-// frontier, so a new pending tile is written with one LDS atomic OR.
+// Invariant: the PEND nibble of a free cell is zero unless the cell is on
+// the frontier, so a new pending tile is written with one LDS atomic OR.  An
+// occupied cell keeps the tile placed there in its nibble.
 template <int W, int B, class Src>
 __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
                                            int G, int p, uint32_t tuple)
@@ -181,10 +182,15 @@ template <int W, int B, class Src>
 __device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunState& st,
                                          DrawCache& dc, int G)
 {
-    for (uint32_t s = st.osum; s; s &= s - 1)
-        g.occ(__builtin_ctz(s)) = 0;
-    // a run that ended on an event leaves frontier cells (and their PEND
-    // nibbles) behind: clear both
+    // occupied cells keep their tiles in PEND, and a run that ended on an
+    // event leaves frontier cells (with their PEND nibbles) behind: clear all
+    for (uint32_t s = st.osum; s; s &= s - 1) {
+        const int w = __builtin_ctz(s);
+        g.occ(w) = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            g.word(Geometry<W>::kPend + 4 * w + k) = 0;
+    }
     for (uint32_t s = st.fsum; s; s &= s - 1) {
         const int w = __builtin_ctz(s);
         g.fr(w) = 0;
@@ -273,11 +279,9 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
         st.fsum &= ~(1u << w);
     st.nf -= 1;
 
-    // take the pending tile and clear its nibble (it leaves the frontier)
-    uint32_t& pwr = g.pend_word(p);
-    const uint32_t pw = pwr;
+    // place the pending tile (its nibble stays: the cell keeps its tile)
+    const uint32_t pw = g.pend_word(p);
     const uint32_t sh = ((uint32_t)p & 7u) * 4u;
-    pwr = pw & ~(15u << sh);
     const uint32_t tuple = m.oriented((int)((pw >> sh) & 15u));
     LaneGrid<W, B>::set_bits(g.occ(w), 1u << bit);
     st.osum |= 1u << w;
@@ -297,6 +301,42 @@ __device__ __forceinline__ int run_assembly(const Src& m, LaneGrid<W, B>& g, Run
     while (!run_over(ev, st, G))
         ev = run_step(m, g, st, dc, G, run, key0, key1, rid_lo, rid_hi);
     return ev;
+}
+
+// True if the shape held in OCC (tiles in PEND) is forced: at every occupied
+// cell, the tiles that its occupied neighbours bond to are exactly that
+// cell's own tile.  For the final shape of a run that ended without an
+// event this means every growth order places the same tile in every cell
+// of the shape and nowhere else (a site outside the shape that any shape
+// cell bonds to would have stayed on the frontier, or ended the run as
+// UNBOUND), and never meets an ambiguous site: every run ends in this shape.
+// The seed cell's nibble is 0, the id of the unrotated seed tile.
+template <int W, int B, class Src>
+__device__ __forceinline__ bool shape_is_forced(const Src& m, LaneGrid<W, B>& g,
+                                                const RunState& st)
+{
+    constexpr int kMask = W * W - 1;
+    bool forced = true;
+    for (uint32_t s = st.osum; s != 0 && forced; s &= s - 1) {
+        const int w = __builtin_ctz(s);
+        for (uint32_t cells = g.occ(w); cells != 0 && forced; cells &= cells - 1) {
+            const int p = (w << 5) | __builtin_ctz(cells);
+            const uint32_t id = (g.pend_word(p) >> ((uint32_t)(p & 7) * 4u)) & 15u;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
+                const int q = (p + delta) & kMask;
+                if (!g.occupied(q))
+                    continue;
+                const uint32_t nq = (g.pend_word(q) >> ((uint32_t)(q & 7) * 4u)) & 15u;
+                // options of the site in direction d + 2 of q's tile: cell p
+                const uint32_t opt = m.options(m.oriented((int)nq), (d + 2) & 3);
+                if (opt != 0 && ((opt >> 4) >= 2u || (opt & 15u) != id))
+                    forced = false;
+            }
+        }
+    }
+    return forced;
 }
 
 // Bounding box of the shape held in OCC (cropping, App. F.6).

@@ -385,11 +385,12 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
     return wsum[w] + incl - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void sort_scan_kernel(BatchArgs a, int klass,
-                                                               uint32_t total)
+// In-place exclusive scan of h[0..total) in blocks of kScanBlock; block b's
+// total goes to sums[b].
+__global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* h, uint32_t total,
+                                                                 uint32_t* sums)
 {
     __shared__ uint32_t wsum[kScanBlock / 64 + 1];
-    uint32_t* h = a.ws.seg_hist[klass];
     const uint32_t i = blockIdx.x * kScanBlock + threadIdx.x;
     const uint32_t v = i < total ? h[i] : 0u;
     uint32_t sum;
@@ -397,21 +398,39 @@ __global__ __launch_bounds__(kScanBlock) void sort_scan_kernel(BatchArgs a, int 
     if (i < total)
         h[i] = excl;
     if (threadIdx.x == 0)
-        a.ws.scan_sums[klass][blockIdx.x] = sum;
+        sums[blockIdx.x] = sum;
 }
 
-__global__ __launch_bounds__(kScanBlock) void sort_scan_sums_kernel(BatchArgs a, int klass,
-                                                                    uint32_t nblocks)
+// In-place exclusive scan of the block totals (one block, any count: each
+// thread takes a run of them); *total_out receives their sum.
+__global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(uint32_t* sums, uint32_t nblocks,
+                                                               uint32_t* total_out)
 {
     __shared__ uint32_t wsum[kScanBlock / 64 + 1];
-    uint32_t* sums = a.ws.scan_sums[klass];
-    const uint32_t v = threadIdx.x < nblocks ? sums[threadIdx.x] : 0u;
+    const uint32_t per = (nblocks + kScanBlock - 1) / kScanBlock;
+    const uint32_t lo = threadIdx.x * per, hi = min(nblocks, lo + per);
+    uint32_t v = 0;
+    for (uint32_t b = lo; b < hi; ++b)
+        v += sums[b];
     uint32_t total;
-    const uint32_t excl = block_exclusive_scan(v, wsum, &total);
-    if (threadIdx.x < nblocks)
-        sums[threadIdx.x] = excl;
+    uint32_t run = block_exclusive_scan(v, wsum, &total);
+    for (uint32_t b = lo; b < hi; ++b) {
+        const uint32_t x = sums[b];
+        sums[b] = run;
+        run += x;
+    }
     if (threadIdx.x == 0)
-        a.ws.counters[kCntCand + klass] = total;
+        *total_out = total;
+}
+
+static void exclusive_scan(uint32_t* h, uint32_t total, uint32_t* sums, uint32_t* total_out,
+                           hipStream_t stream)
+{
+    const uint32_t blocks = (total + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(blocks), dim3(kScanBlock), 0, stream, h, total,
+                       sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, stream, sums, blocks,
+                       total_out);
 }
 
 // One block per segment: place its candidates with LDS cursors per bucket.
@@ -430,6 +449,91 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
     for (uint32_t i = threadIdx.x; i < n; i += 256) {
         const uint32_t pos = atomicAdd(&cursor[size_key(sz[i])], 1u);
         a.ws.sorted[klass][pos] = ix[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// prove<W>: one lane per candidate (in size order) replays its first run and
+// checks whether the shape is forced (shape_is_forced): then every run ends
+// in it and the record is final without the repeat runs -- DET, run 0's
+// size and hash, (size - 1) * R placements.  The other candidates are kept,
+// in queue order, for the repeat runs: keep[pos] holds the candidate or
+// kNoCandidate, and chunk_cnt[c] the kept count of queue chunk c (64
+// positions; every chunk below n/64 is written).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoCandidate = 0xFFFFFFFFu;
+
+template <int W, int TM>
+__global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
+{
+    using Geo = Geometry<W>;
+    const uint64_t first = slice_first(a);
+    jatam_result_t* const out = slice_out(a);
+    __shared__ uint32_t smem[Geo::kLaneWords * 64];
+    __shared__ uint4 cache_mem[kShapeCache];
+    LaneGrid<W, 64> g{smem + threadIdx.x};
+    g.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
+    RunState st{0, 0, 0, 0, 0, false};
+    WaveTally tally{{0, 0, 0, 0}};
+    const uint32_t count = a.ws.counters[kCntCand + klass];
+    const uint32_t* queue = a.ws.sorted[klass];
+    uint32_t* keep = a.ws.cand_idx[klass];
+    uint32_t* chunk_cnt = a.ws.chunk_cnt[klass];
+    const uint32_t nchunks = (uint32_t)((a.n + 63) / 64);
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t pos = c * 64 + (uint32_t)lane_id();
+        const bool active = pos < count;
+        uint32_t idx = 0;
+        bool forced = false;
+        Geno gd{0, 0, 0, 0, false};
+        if (active) {
+            idx = queue[pos];
+            gd = fetch_geno(a, first, idx);
+            const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
+            const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
+                                        (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
+            forced = ev == kEvNone && shape_is_forced(src, g, st);
+        }
+        const uint32_t h = det_hash(g, a, cache, forced, st.size, gd.grid);
+        if (forced)
+            out[idx] = jatam_result_t{JATAM_DET, st.size, h, (st.size - 1) * a.runs};
+        tally.add(forced, JATAM_DET);
+        const bool kept = active && !forced;
+        if (active)
+            keep[pos] = kept ? idx : kNoCandidate;
+        const uint32_t kc = (uint32_t)__popcll(__ballot(kept));
+        if (lane_id() == 0)
+            chunk_cnt[c] = kc;
+    }
+    tally.flush(a.tally);
+}
+
+// The candidate count before the proof, kept for the compaction (the scan
+// of the kept counts overwrites kCntCand).
+__global__ void copy_count_kernel(const BatchArgs a, int klass)
+{
+    if (threadIdx.x == 0)
+        a.ws.counters[kCntCandAll + klass] = a.ws.counters[kCntCand + klass];
+}
+
+// Kept candidates to the front of the queue, in order (one wave per chunk).
+__global__ __launch_bounds__(256) void compact_kernel(const BatchArgs a, int klass)
+{
+    const uint32_t count_all = (uint32_t)((a.n + 63) / 64) * 64;
+    const uint32_t pos = blockIdx.x * 256 + threadIdx.x;
+    if (pos >= count_all)
+        return;
+    const uint32_t c = pos >> 6;
+    const bool in_queue = pos < a.ws.counters[kCntCandAll + klass];
+    const uint32_t v = in_queue ? a.ws.cand_idx[klass][pos] : kNoCandidate;
+    const bool kept = v != kNoCandidate;
+    const uint64_t m = __ballot(kept);
+    if (kept) {
+        const uint32_t base = a.ws.chunk_cnt[klass][c] + a.ws.chunk_sums[klass][c / kScanBlock];
+        a.ws.sorted[klass][base + (uint32_t)__popcll(m & lanes_below())] = v;
     }
 }
 
@@ -693,23 +797,32 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         a.refill = launch[k].refill;
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
         a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64);
-        begin(kStageFirst + 3 * k);
+        begin(kStageFirst + kStagesPerClass * k);
         if (k == 0)
             hipLaunchKernelGGL((first_run_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
         else
             hipLaunchKernelGGL((first_run_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
-        end(kStageFirst + 3 * k);
-        begin(kStageSort + 3 * k);
+        end(kStageFirst + kStagesPerClass * k);
+        begin(kStageSort + kStagesPerClass * k);
         hipLaunchKernelGGL(sort_hist_kernel, dim3(nb), dim3(256), 0, stream, a, k);
-        const uint32_t entries = (uint32_t)kSizeBuckets * nb;
-        const uint32_t scan_blocks = (entries + kScanBlock - 1) / kScanBlock;
-        hipLaunchKernelGGL(sort_scan_kernel, dim3(scan_blocks), dim3(kScanBlock), 0, stream, a, k,
-                           entries);
-        hipLaunchKernelGGL(sort_scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, stream, a, k,
-                           scan_blocks);
+        exclusive_scan(a.ws.seg_hist[k], (uint32_t)kSizeBuckets * nb, a.ws.scan_sums[k],
+                       a.ws.counters + kCntCand + k, stream);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nb), dim3(256), 0, stream, a, k);
-        end(kStageSort + 3 * k);
-        begin(kStageRepeat + 3 * k);
+        end(kStageSort + kStagesPerClass * k);
+        // forced shapes are final; the rest are compacted for the repeat runs
+        begin(kStageProve + kStagesPerClass * k);
+        if (k == 0)
+            hipLaunchKernelGGL((prove_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
+        else
+            hipLaunchKernelGGL((prove_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
+        const uint32_t qchunks = (uint32_t)nchunks;
+        hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, stream, a, k);
+        exclusive_scan(a.ws.chunk_cnt[k], qchunks, a.ws.chunk_sums[k],
+                       a.ws.counters + kCntCand + k, stream);
+        hipLaunchKernelGGL(compact_kernel, dim3((qchunks * 64 + 255) / 256), dim3(256), 0, stream,
+                           a, k);
+        end(kStageProve + kStagesPerClass * k);
+        begin(kStageRepeat + kStagesPerClass * k);
         // the bond table holds colours 0..7
         const bool table = a.c <= 8;
         if (k == 0 && table)
@@ -720,7 +833,7 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             hipLaunchKernelGGL((repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a, 1);
         else
             hipLaunchKernelGGL((repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a, 1);
-        end(kStageRepeat + 3 * k);
+        end(kStageRepeat + kStagesPerClass * k);
     }
 }
 

@@ -31,6 +31,7 @@ enum {
     kCntCand = 0,     // [2] DET candidates per grid class (written by the sort)
     kCntDiff = 2,     // record comparison flag of the autotuner
     kCntSlice = 3,    // slice counter of a graph-replayed enumeration
+    kCntCandAll = 4,  // [2] candidates before the forced-shape proof
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
@@ -44,6 +45,8 @@ struct DeviceWorkspace {
     uint32_t* seg_count[2];   // [max_blocks] candidates staged by each wave
     uint32_t* seg_hist[2];    // [kSizeBuckets * max_blocks] bucket-major counts
     uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
+    uint32_t* chunk_cnt[2];   // [max_n / 64 + 1] kept candidates per queue chunk
+    uint32_t* chunk_sums[2];  // [max_n / 64 / kScanBlock + 1] block totals of their scan
     uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks + 1)] per-wave segments
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
@@ -71,12 +74,14 @@ struct BatchArgs {
     DeviceWorkspace ws;
 };
 
-// Pipeline stages, in launch order (timing hook): three per grid class.
+// Pipeline stages, in launch order (timing hook): four per grid class.
 enum {
-    kStageFirst = 0,    // + 3 * grid class
-    kStageSort = 1,     // + 3 * grid class
-    kStageRepeat = 2,   // + 3 * grid class
-    kStages = 6,
+    kStageFirst = 0,    // + kStagesPerClass * grid class
+    kStageSort = 1,
+    kStageProve = 2,
+    kStageRepeat = 3,
+    kStagesPerClass = 4,
+    kStages = 8,
 };
 
 // Launch parameters of one grid class: first-run refill threshold and the

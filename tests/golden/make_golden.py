@@ -22,14 +22,18 @@ from oracle import ref  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def slice_summary(recs, s0, e0, c0, runs):
+def slice_summary(recs, s0, e0, c0, f0, runs):
     det = recs["cls"] == 3
     size = recs["size"].astype(np.int64)
     steps = recs["steps"].astype(np.int64)
+    s0 = s0.astype(np.int64)
     # how the work splits over a pipeline: genotypes the seed alone decides
-    # (0 placements), first runs, and the repeat runs of candidates whose
-    # first run drew a random word and ended without an event
+    # (0 placements) and first runs; then the candidates (first run drew a
+    # random word and ended without an event): those whose first-run shape
+    # is forced are final after that run, the others need the repeat runs
     cand = (e0 == 0) & (c0 == 1) & (runs > 1)
+    forced = cand & (f0 == 1)
+    unproven = cand & (f0 == 0)
     first_only = ~cand
     return {
         "sha256": hashlib.sha256(recs.tobytes()).hexdigest(),
@@ -37,14 +41,19 @@ def slice_summary(recs, s0, e0, c0, runs):
         "steps": int(steps.sum()),
         "det_size": int(size[det].sum()),
         "work": {
-            "run0_steps": int(s0.astype(np.int64).sum()),
+            "run0_steps": int(s0.sum()),
             "monomer_det": int(np.sum(det & (size == 1))),
             "run0_det": int(np.sum(det & first_only & (size > 1))),
             "run0_det_size": int(size[det & first_only & (size > 1)].sum()),
             "candidates": int(cand.sum()),
-            "repeat_steps": int((steps[cand] - s0[cand]).sum()),
-            "repeat_det": int(np.sum(det & cand)),
-            "repeat_det_size": int(size[det & cand].sum()),
+            "cand_steps0": int(s0[cand].sum()),
+            "cand_size": int(size[cand].sum()),
+            "forced": int(forced.sum()),
+            "forced_size": int(size[forced].sum()),
+            "unproven": int(unproven.sum()),
+            "unproven_steps": int(steps[unproven].sum()),
+            "unproven_det": int(np.sum(det & unproven)),
+            "unproven_det_size": int(size[det & unproven].sum()),
         },
     }
 
@@ -63,8 +72,9 @@ def make(t, grid, runs, seed, total, slice_n, path):
     shapes = {}
     for first in range(0, total, slice_n):
         n = min(slice_n, total - first)
-        recs, s0, e0, c0 = ref.classify_range_run0(first, n, t, grid=grid, runs=runs, seed=seed)
-        s = slice_summary(recs, s0, e0, c0, runs)
+        recs, s0, e0, c0, f0 = ref.classify_range_run0(first, n, t, grid=grid, runs=runs,
+                                                       seed=seed, forced=True)
+        s = slice_summary(recs, s0, e0, c0, f0, runs)
         for key, cnt in shape_counts(recs).items():
             shapes[key] = shapes.get(key, 0) + cnt
         s["first"] = first

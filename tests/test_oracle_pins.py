@@ -428,3 +428,52 @@ def test_widest_genome_c16_t4():
     g = (1 << 64) - 1
     rec = ref.classify_one(g, 4, c=16)
     assert rec[0] in (ref.UNBOUND, ref.ND_SITE, ref.ND_RUNS, ref.DET)
+
+
+# ---------------------------------------------------------------------------
+# Forced shapes: a first-run shape in which every cell's occupied neighbours
+# bond to that cell's own tile only.  Pinned against the classification
+# itself (every forced genotype is DET with (size - 1) * R placements, for
+# every R) and against the independent brute-force explorer (every growth
+# order ends in that one shape, with no event).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t,grid,space", [(1, 16, 4096), (2, 16, 1 << 24), (3, 16, 1 << 36),
+                                          (3, 32, 1 << 36)])
+def test_forced_shapes_classify_det_for_every_run_count(t, grid, space):
+    rng = np.random.default_rng(t * 100 + grid)
+    n = min(2048, space)
+    seen = 0
+    for first in rng.integers(0, max(1, space - n), size=4):
+        for runs in (2, 7, 20):
+            recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), n, t, grid=grid,
+                                                           runs=runs, forced=True)
+            forced = f0 == 1
+            seen += int(np.sum(forced & (c0 == 1)))
+            assert np.all(e0[forced] == 0)
+            assert np.all(recs["cls"][forced] == ref.DET)
+            placed = recs["size"][forced].astype(np.int64) - 1
+            want = np.where(c0[forced] == 1, placed * runs, placed)
+            assert np.array_equal(recs["steps"][forced].astype(np.int64), want)
+    assert seen > 0     # forced shapes whose first run drew random words
+
+
+def test_forced_shapes_are_the_only_terminal_of_every_order():
+    """Forced genotypes of S_{2,8} whose first run drew random words: the
+    brute-force explorer finds no event and exactly one terminal assembly,
+    the first run's shape."""
+    rng = np.random.default_rng(77)
+    starts = rng.integers(0, (1 << 24) - 4096, size=4)
+    checked = 0
+    for first in starts:
+        recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), 4096, 2, forced=True)
+        for i in np.nonzero((f0 == 1) & (c0 == 1))[0][:12]:
+            g = int(first) + int(i)
+            ex = bf.explore(g, 2, 8, 16, cap=20_000)
+            if ex.capped:
+                continue
+            assert not ex.events, g
+            assert len(ex.terminals) == 1, g
+            shape = next(iter(ex.terminals))
+            assert len(shape) == recs["size"][i], g
+            checked += 1
+    assert checked >= 20
