@@ -239,36 +239,70 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
     int w = 0;
     uint32_t fw = 0;
     if constexpr (W == 16) {
-        // 8 frontier words: load all, pick the word by prefix counts, no loop
-        uint32_t f[Geometry<W>::kWords];
-#pragma unroll
-        for (int k = 0; k < Geometry<W>::kWords; ++k)
-            f[k] = g.fr(k);
-        uint32_t acc = 0, rank = 0;
-#pragma unroll
-        for (int k = 0; k < Geometry<W>::kWords; ++k) {
-            const uint32_t c = __popc(f[k]);
-            const bool hit = j >= acc && j < acc + c;
-            fw = hit ? f[k] : fw;
-            w = hit ? k : w;
-            rank = hit ? j - acc : rank;
-            acc += c;
-        }
-        if (acc != st.nf)
+        // 8 frontier words, no loop: inclusive prefix counts p0..p7; the
+        // word holding site j is the number of prefixes <= j; the word and
+        // its exclusive prefix are picked by binary trees of selects on that
+        // index (scalars throughout: an array picked at run time would go to
+        // scratch memory)
+        const uint32_t f0 = g.fr(0), f1 = g.fr(1), f2 = g.fr(2), f3 = g.fr(3);
+        const uint32_t f4 = g.fr(4), f5 = g.fr(5), f6 = g.fr(6), f7 = g.fr(7);
+        const uint32_t p0 = __popc(f0), p1 = p0 + __popc(f1), p2 = p1 + __popc(f2);
+        const uint32_t p3 = p2 + __popc(f3), p4 = p3 + __popc(f4), p5 = p4 + __popc(f5);
+        const uint32_t p6 = p5 + __popc(f6), p7 = p6 + __popc(f7);
+        if (p7 != st.nf)
             return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
-        j = rank;
+        const uint32_t wi = (uint32_t)(p0 <= j) + (uint32_t)(p1 <= j) + (uint32_t)(p2 <= j) +
+                            (uint32_t)(p3 <= j) + (uint32_t)(p4 <= j) + (uint32_t)(p5 <= j) +
+                            (uint32_t)(p6 <= j);
+        const bool b0 = (wi & 1u) != 0, b1 = (wi & 2u) != 0, b2 = (wi & 4u) != 0;
+        const uint32_t fa = b0 ? f1 : f0, fb = b0 ? f3 : f2, fc = b0 ? f5 : f4, fd = b0 ? f7 : f6;
+        const uint32_t ea = b0 ? p0 : 0u, eb = b0 ? p2 : p1, ec = b0 ? p4 : p3, ed = b0 ? p6 : p5;
+        const uint32_t fab = b1 ? fb : fa, fcd = b1 ? fd : fc;
+        const uint32_t eab = b1 ? eb : ea, ecd = b1 ? ed : ec;
+        fw = b2 ? fcd : fab;
+        j -= b2 ? ecd : eab;
+        w = (int)wi;
     } else {
+        // the nonzero frontier words four at a time: four independent LDS
+        // reads per round instead of one round trip per word
         uint32_t fs = st.fsum;
-        while (fs != 0) {
-            w = __builtin_ctz(fs);
-            fw = g.fr(w);
-            const uint32_t c = __popc(fw);
-            if (j < c)
-                break;
-            j -= c;
-            fs &= fs - 1;
+        bool found = false;
+        while (fs != 0 && !found) {
+            const uint32_t s1 = fs & (fs - 1), s2 = s1 & (s1 - 1), s3 = s2 & (s2 - 1);
+            const int w0 = __builtin_ctz(fs);
+            const int w1 = s1 ? __builtin_ctz(s1) : w0;
+            const int w2 = s2 ? __builtin_ctz(s2) : w0;
+            const int w3 = s3 ? __builtin_ctz(s3) : w0;
+            const uint32_t f0 = g.fr(w0);
+            const uint32_t f1 = s1 ? g.fr(w1) : 0u;
+            const uint32_t f2 = s2 ? g.fr(w2) : 0u;
+            const uint32_t f3 = s3 ? g.fr(w3) : 0u;
+            const uint32_t c0 = __popc(f0), c1 = __popc(f1), c2 = __popc(f2), c3 = __popc(f3);
+            if (j < c0) {
+                w = w0;
+                fw = f0;
+                found = true;
+            } else if (j < c0 + c1) {
+                w = w1;
+                fw = f1;
+                j -= c0;
+                found = true;
+            } else if (j < c0 + c1 + c2) {
+                w = w2;
+                fw = f2;
+                j -= c0 + c1;
+                found = true;
+            } else if (j < c0 + c1 + c2 + c3) {
+                w = w3;
+                fw = f3;
+                j -= c0 + c1 + c2;
+                found = true;
+            } else {
+                j -= c0 + c1 + c2 + c3;
+                fs = s3 & (s3 - 1);
+            }
         }
-        if (fs == 0)
+        if (!found)
             return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
     }
     const int bit = select_bit(fw, j);
