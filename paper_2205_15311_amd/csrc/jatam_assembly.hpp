@@ -160,6 +160,7 @@ struct DrawCache {
     uint32_t block;
     uint32_t w0, w1, w2, w3;
 
+    __device__ __forceinline__ void reset() { block = 0xFFFFFFFFu; }
     __device__ __forceinline__ void fill(const Words4& v)
     {
         w0 = v.w[0];
@@ -174,13 +175,106 @@ struct DrawCache {
         const uint32_t hi = (k & 1u) ? w3 : w2;
         return (k & 2u) ? hi : lo;
     }
+    // random word s of run `run`: word s mod 4 of counter block s / 4
+    __device__ __forceinline__ uint32_t draw(uint32_t s, int run, uint32_t key0, uint32_t key1,
+                                             uint32_t rid_lo, uint32_t rid_hi)
+    {
+        const uint32_t blk = s >> 2;
+        if (blk != block) {
+            fill(philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
+            block = blk;
+        }
+        return word(s & 3u);
+    }
 };
+
+// Two Philox blocks of a run, one of even and one of odd block index, so
+// that a block can be computed before the run reaches it.  A wave whose
+// lanes run out of phase computes blocks whenever any lane needs one; with
+// one block per lane that happens on most steps with few lanes active.  With
+// two, every lane fills the block it lacks (its current one, else the next)
+// at each such point, so all lanes share one computation about every fourth
+// step (see prefetch).  draw() still computes a missing block itself.
+struct DrawPair {
+    uint32_t te, to;                    // block index held (all ones: none)
+    uint32_t e0, e1, e2, e3;            // the even block
+    uint32_t o0, o1, o2, o3;            // the odd block
+
+    // Members are only ever combined by value selects: choosing between two
+    // members as lvalues (or storing through such a choice) makes the
+    // compiler address the struct by a run-time offset, in scratch memory.
+    __device__ __forceinline__ static uint32_t pick(bool c, uint32_t x, uint32_t y)
+    {
+        return c ? x : y;
+    }
+    __device__ __forceinline__ void reset()
+    {
+        te = 0xFFFFFFFFu;
+        to = 0xFFFFFFFFu;
+    }
+    // te only ever holds an even index and to an odd one
+    __device__ __forceinline__ bool has(uint32_t blk) const { return te == blk || to == blk; }
+    __device__ __forceinline__ void put(uint32_t blk, const Words4& v)
+    {
+        const bool odd = (blk & 1u) != 0;
+        to = pick(odd, blk, to);
+        o0 = pick(odd, v.w[0], o0);
+        o1 = pick(odd, v.w[1], o1);
+        o2 = pick(odd, v.w[2], o2);
+        o3 = pick(odd, v.w[3], o3);
+        te = pick(odd, te, blk);
+        e0 = pick(odd, e0, v.w[0]);
+        e1 = pick(odd, e1, v.w[1]);
+        e2 = pick(odd, e2, v.w[2]);
+        e3 = pick(odd, e3, v.w[3]);
+    }
+    // the block this lane should compute now, given its next draw index s:
+    // block s/4 if missing, else block s/4 + 1 if missing; false if neither
+    __device__ __forceinline__ bool wanted(uint32_t s, uint32_t& blk) const
+    {
+        const uint32_t b = s >> 2;
+        const bool cur = !has(b);
+        blk = cur ? b : b + 1u;
+        return cur || !has(b + 1u);
+    }
+    __device__ __forceinline__ uint32_t draw(uint32_t s, int run, uint32_t key0, uint32_t key1,
+                                             uint32_t rid_lo, uint32_t rid_hi)
+    {
+        const uint32_t blk = s >> 2;
+        if (!has(blk))
+            put(blk, philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
+        const bool odd = (blk & 1u) != 0;
+        const uint32_t k = s & 3u;
+        const uint32_t x0 = pick(odd, o0, e0), x1 = pick(odd, o1, e1);
+        const uint32_t x2 = pick(odd, o2, e2), x3 = pick(odd, o3, e3);
+        const uint32_t lo = pick((k & 1u) != 0, x1, x0);
+        const uint32_t hi = pick((k & 1u) != 0, x3, x2);
+        return pick((k & 2u) != 0, hi, lo);
+    }
+};
+
+// Wave-wide Philox fill for lanes that keep a DrawPair: when the next draw
+// of any stepping lane lacks its block, every stepping lane computes the
+// block it lacks, so one pass of the generator serves the whole wave.  Call
+// with every lane of the wave present (it takes a ballot).
+__device__ __forceinline__ void prefetch_draws(DrawPair& dp, bool stepping, const RunState& st,
+                                               int run, uint32_t key0, uint32_t key1,
+                                               uint32_t rid_lo, uint32_t rid_hi)
+{
+    const uint32_t s = (uint32_t)st.steps;
+    const bool need = stepping && st.nf >= 2 && !dp.has(s >> 2);
+    if (__ballot(need) == 0)
+        return;
+    uint32_t blk = 0;
+    if (stepping && dp.wanted(s, blk))
+        dp.put(blk, philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
+}
 
 // Starts a run: clears what the previous run touched, places the seed
 // (tile 0, unrotated) at the centre and checks its neighbours.
-template <int W, int B, class Src>
+template <int W, int B, class Src, class Draws>
 __device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunState& st,
-                                         DrawCache& dc, int G)
+                                         Draws& dc, int G)
 {
     // occupied cells keep their tiles in PEND, and a run that ended on an
     // event leaves frontier cells (with their PEND nibbles) behind: clear all
@@ -203,7 +297,7 @@ __device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunSta
     st.size = 1;
     st.steps = 0;
     st.choice = false;
-    dc.block = 0xFFFFFFFFu;
+    dc.reset();
     const int seed_pos = (G / 2 - 1) * W + (G / 2 - 1);
     g.occ(seed_pos >> 5) = 1u << (seed_pos & 31);
     st.osum = 1u << (seed_pos >> 5);
@@ -220,20 +314,15 @@ __device__ __forceinline__ bool run_over(int ev, const RunState& st, int G)
 // One step: draw the frontier site of rank floor(u*|F|/2^32) in row-major
 // order (u = Philox word `steps` of this run's stream; no draw is needed with
 // one site), place its pending tile and check the new neighbours.
-template <int W, int B, class Src>
+template <int W, int B, class Src, class Draws>
 __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunState& st,
-                                        DrawCache& dc, int G, int run, uint32_t key0,
+                                        Draws& dc, int G, int run, uint32_t key0,
                                         uint32_t key1, uint32_t rid_lo, uint32_t rid_hi)
 {
     uint32_t j = 0;
     if (st.nf >= 2) {
         st.choice = true;
-        const uint32_t blk = (uint32_t)st.steps >> 2;
-        if (blk != dc.block) {
-            dc.fill(philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
-            dc.block = blk;
-        }
-        j = __umulhi(dc.word((uint32_t)st.steps & 3u), st.nf);
+        j = __umulhi(dc.draw((uint32_t)st.steps, run, key0, key1, rid_lo, rid_hi), st.nf);
     }
     // the j-th frontier site in row-major order
     int w = 0;

@@ -182,8 +182,8 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     cache.clear(lane_id());
     __syncthreads();
     RunState st{0, 0, 0, 0, 0, false};
-    DrawCache dc;
-    dc.block = 0xFFFFFFFFu;
+    DrawPair dc;
+    dc.reset();
 
     const uint32_t wave = blockIdx.x, nwaves = gridDim.x;
     const uint32_t nchunks = (uint32_t)((a.n + 63) / 64);
@@ -274,7 +274,10 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
             continue;
         }
         // -- one step of every busy lane ---------------------------------------
-        if (busy && !run_over(ev, st, gd.grid))
+        const bool stepping = busy && !run_over(ev, st, gd.grid);
+        prefetch_draws(dc, stepping, st, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
+                       (uint32_t)(gd.rng_id >> 32));
+        if (stepping)
             ev = run_step(m, g, st, dc, gd.grid, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
                           (uint32_t)(gd.rng_id >> 32));
         // -- lanes whose first run is over ----------------------------------
