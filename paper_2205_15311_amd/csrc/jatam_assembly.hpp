@@ -270,11 +270,10 @@ __device__ __forceinline__ void prefetch_draws(DrawPair& dp, bool stepping, cons
         dp.put(blk, philox4x32_10(blk, (uint32_t)run, rid_lo, rid_hi, key0, key1));
 }
 
-// Starts a run: clears what the previous run touched, places the seed
-// (tile 0, unrotated) at the centre and checks its neighbours.
-template <int W, int B, class Src, class Draws>
-__device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunState& st,
-                                         Draws& dc, int G)
+// Clears what the previous run touched and places the seed (tile 0,
+// unrotated) at the centre; returns the seed's cell.
+template <int W, int B, class Draws>
+__device__ __forceinline__ int run_clear(LaneGrid<W, B>& g, RunState& st, Draws& dc, int G)
 {
     // occupied cells keep their tiles in PEND, and a run that ended on an
     // event leaves frontier cells (with their PEND nibbles) behind: clear all
@@ -301,7 +300,51 @@ __device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunSta
     const int seed_pos = (G / 2 - 1) * W + (G / 2 - 1);
     g.occ(seed_pos >> 5) = 1u << (seed_pos & 31);
     st.osum = 1u << (seed_pos >> 5);
+    return seed_pos;
+}
+
+// Starts a run: clears what the previous run touched, places the seed
+// (tile 0, unrotated) at the centre and checks its neighbours.
+template <int W, int B, class Src, class Draws>
+__device__ __forceinline__ int run_start(const Src& m, LaneGrid<W, B>& g, RunState& st,
+                                         Draws& dc, int G)
+{
+    const int seed_pos = run_clear(g, st, dc, G);
     return update_site(m, g, st, G, seed_pos, m.seed());
+}
+
+// run_start for a seed whose four site codes are already known (byte d of
+// `seed_opts` is the options code of the seed's site in direction d).  In
+// the cleared grid every neighbour of the seed is free and off the
+// frontier, so update_site reduces to the ring test and the frontier
+// insertions: no grid reads, no options lookups.
+template <int W, int B, class Draws>
+__device__ __forceinline__ int run_start_known(LaneGrid<W, B>& g, RunState& st, Draws& dc,
+                                               int G, uint32_t seed_opts)
+{
+    constexpr int kMask = W * W - 1;
+    const int p = run_clear(g, st, dc, G);
+    bool unbound = false, ambiguous = false;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
+        const int q = (p + delta) & kMask;
+        const uint32_t opt = (seed_opts >> (8 * d)) & 0x3Fu;
+        const int qx = q & (W - 1), qy = q >> Geometry<W>::kLogW;
+        const bool ring = qx >= G - 1 || qy >= G - 1;
+        const bool has = opt != 0;
+        const bool multi = (opt >> 4) >= 2;
+        unbound = unbound || (has && ring);
+        ambiguous = ambiguous || (has && !ring && multi);
+        if (has && !ring && !multi) {
+            const uint32_t sh = ((uint32_t)q & 7u) * 4u;
+            LaneGrid<W, B>::set_bits(g.fr(q >> 5), 1u << (q & 31));
+            LaneGrid<W, B>::set_bits(g.pend_word(q), (opt & 15u) << sh);
+            st.fsum |= 1u << (q >> 5);
+            st.nf += 1;
+        }
+    }
+    return unbound ? kEvUnbound : ambiguous ? kEvAmbig : kEvNone;
 }
 
 // A run is over once an event happened or the frontier is empty.  Every step

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     const uint64_t first = slice_first(a);
     jatam_result_t* const out = slice_out(a);
     __shared__ uint32_t smem[Geo::kLaneWords * 64];
-    __shared__ uint32_t ring[kRing];
+    __shared__ uint32_t ring[kRing];       // survivor indices
+    __shared__ uint32_t ring_opt[kRing];   // their seeds' four site codes
     __shared__ uint4 cache_mem[kShapeCache];
     LaneGrid<W, 64> g{smem + threadIdx.x};
     g.clear_all();
@@ -216,6 +217,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 }
                 bool done = false, keep = false;
                 int cls = 0;
+                uint32_t opts = 0;
                 if (in_range) {
                     const Geno s = fetch_geno(a, first, i);
                     if (!s.valid) {
@@ -231,6 +233,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                             const uint32_t opt = site_options(sm, seed, d);
                             ambiguous = ambiguous || (opt >> 4) >= 2;
                             bonds = bonds || opt != 0;
+                            opts |= opt << (8 * d);
                         }
                         if (ambiguous) {
                             out[i] = jatam_result_t{JATAM_ND_SITE, 1, 0u, 0};
@@ -247,8 +250,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 }
                 tally.add(done, cls);
                 const uint64_t km = __ballot(keep);
-                if (keep)
-                    ring[(head + queued + (uint32_t)__popcll(km & lanes_below())) % kRing] = i;
+                if (keep) {
+                    const uint32_t slot = (head + queued + (uint32_t)__popcll(km & lanes_below())) % kRing;
+                    ring[slot] = i;
+                    ring_opt[slot] = opts;
+                }
                 queued += (uint32_t)__popcll(km);
                 next_chunk += nwaves;
             }
@@ -257,10 +263,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
             if (!busy) {
                 const uint32_t rank = (uint32_t)__popcll(idle & lanes_below());
                 if (rank < take) {
-                    idx = ring[(head + rank) % kRing];
+                    const uint32_t slot = (head + rank) % kRing;
+                    idx = ring[slot];
                     gd = fetch_geno(a, first, idx);
                     m.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
-                    ev = run_start(m, g, st, dc, gd.grid);
+                    ev = run_start_known(g, st, dc, gd.grid, ring_opt[slot]);
                     busy = true;
                 }
             }
