@@ -127,11 +127,14 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
         fw[d] = g.fr(q[d] >> 5);
         pw[d] = g.pend_word(q[d]);
     }
+    // p lies in the box ([0, G-2]^2), so a neighbour is on the ring exactly
+    // when p is on the box's edge in that direction (N and W wrap round the
+    // torus onto row or column W-1)
+    const int px = p & (W - 1), py = p >> Geometry<W>::kLogW;
     bool unbound = false, ambiguous = false;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-        const int qx = q[d] & (W - 1), qy = q[d] >> Geometry<W>::kLogW;
-        const bool ring = qx >= G - 1 || qy >= G - 1;
+        const bool ring = d == 0 ? py == 0 : d == 1 ? px == G - 2 : d == 2 ? py == G - 2 : px == 0;
         const uint32_t bit = (uint32_t)q[d] & 31u;
         const bool has = opt[d] != 0;
         const bool free = ((ow[d] >> bit) & 1u) == 0;

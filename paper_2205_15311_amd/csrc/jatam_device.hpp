@@ -93,9 +93,12 @@ struct Model {
     Word reps;           // bit 4k+3 set for representative oriented tiles
     int c;               // colour count
 
+    // by value selects: a choice between the members as lvalues lets the
+    // compiler address the struct by a run-time offset, in scratch memory
+    __device__ __forceinline__ static Word pick(bool c, Word x, Word y) { return c ? x : y; }
     __device__ __forceinline__ Word side_col(int s) const
     {
-        return s == 0 ? cols0 : s == 1 ? cols1 : s == 2 ? cols2 : cols3;
+        return pick(s < 2, pick(s == 0, cols0, cols1), pick(s == 2, cols2, cols3));
     }
 };
 
@@ -196,11 +199,26 @@ __device__ __forceinline__ uint32_t seed_tile(const Model<TM>& m)
     return (uint32_t)m.tiles & 0xFFFFu;
 }
 
+// Colour k in every nibble of a model word (k < 16): the byte kk copied to
+// all four bytes by a byte permute.  (Written as k * 0x11111111 it becomes a
+// full 32-bit multiply, a quarter-rate instruction.)
+template <class Word>
+__device__ __forceinline__ Word nibble_splat(uint32_t k)
+{
+    const uint32_t b = k | (k << 4);
+    const uint32_t w = __builtin_amdgcn_perm(b, b, 0u);   // selector 0: byte 0 everywhere
+    if constexpr (sizeof(Word) == 8)
+        return ((uint64_t)w << 32) | w;
+    else
+        return w;
+}
+
 // Bonding options of the empty site next to a placed tile (colour tuple
 // `tuple`) in direction d: the distinct representatives that show the
 // partner of the tile's side-d colour on their side facing back.  Returns
 // min(count, 2) in bits 4..5 and the lowest representative id in bits 0..3
-// (0 when nothing bonds).
+// (0 when nothing bonds).  No branches: a colour without a partner masks
+// the match instead.
 template <int TM>
 __device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tuple, int d)
 {
@@ -209,21 +227,19 @@ __device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tu
     const int x = (int)((tuple >> (4 * d)) & 15u);
     // partner colour: 1<->2, 3<->4, ...; 0 and a last odd colour have none
     const int p = ((x + 1) ^ 1) - 1;
-    if (p < 0 || p >= m.c)
-        return 0;
-    const Word v = m.side_col((d + 2) & 3) ^ (M::kOnes * (Word)p);
+    const bool bonds = p >= 0 && p < m.c;
+    const Word v = m.side_col((d + 2) & 3) ^ nibble_splat<Word>((uint32_t)p & 15u);
     // high bit of each nibble set iff the nibble is nonzero (no carries escape)
     const Word nonzero = v | ((v & M::kLow3) + M::kLow3);
-    const Word match = ~nonzero & m.reps;
-    if (match == 0)
-        return 0;
+    const Word match = bonds ? (~nonzero & m.reps) : (Word)0;
+    const Word lowest = match != 0 ? match : (Word)1;   // ctz of 0 is undefined
     uint32_t id;
     if constexpr (TM == 2)
-        id = (uint32_t)__builtin_ctz((uint32_t)match) >> 2;
+        id = (uint32_t)__builtin_ctz((uint32_t)lowest) >> 2;
     else
-        id = (uint32_t)__builtin_ctzll((uint64_t)match) >> 2;
+        id = (uint32_t)__builtin_ctzll((uint64_t)lowest) >> 2;
     const uint32_t count = (match & (match - 1)) ? 2u : 1u;
-    return (count << 4) | id;
+    return match != 0 ? ((count << 4) | id) : 0u;
 }
 
 // ---------------------------------------------------------------------------
