@@ -531,6 +531,88 @@ __device__ __forceinline__ ShapeBox crop(LaneGrid<W, B>& g, int G)
     return ShapeBox{xmin, ymin, xmax - xmin + 1, ymax - ymin + 1};
 }
 
+// True if the shape held in OCC (tiles in PEND), left by a run that ended
+// without an event, is guarded: every run ends in it.  Call an edge from an
+// occupied cell q to an occupied neighbour p good when q's tile admits
+// exactly p's tile at p, and a conflict when it admits anything else there.
+// The shape is guarded when, for every conflict q -> p with p not the seed,
+// every path of good edges from the seed to q passes through p.
+//
+// Why that suffices: in any growth order a tile is placed only from the
+// frontier, where it arrived over an edge from a tile placed before it.  By
+// induction over the placements, every tile so far is the shape's own tile
+// in a cell of the shape, reached from the seed over good edges through
+// cells placed before it; so a conflicting q is never placed while p is
+// empty, and q's wrong option at p never counts.  No site outside the shape
+// can be bonded to (run 0 would have grown there or met an event), so the
+// run places the shape exactly, never meets an event, and places all of it
+// (every cell of the shape has a good edge from a cell placed before it in
+// run 0).  With no conflicts this is shape_is_forced.
+//
+// The flood fills run on 64-bit bitmaps of the shape's bounding box, which
+// must fit 8 x 8; a larger shape is tested with shape_is_forced instead.
+template <int W, int B, class Src>
+__device__ __forceinline__ bool shape_is_guarded(const Src& m, LaneGrid<W, B>& g,
+                                                 const RunState& st, int G)
+{
+    constexpr int kMask = W * W - 1;
+    const ShapeBox bx = crop(g, G);
+    if (bx.w > 8 || bx.h > 8)
+        return shape_is_forced(m, g, st);
+    // per cell p of the 8 x 8 frame, bit (y - ymin) * 8 + (x - xmin):
+    // good_d / conf_d: the edge into p from its neighbour in direction d
+    uint64_t shape = 0, good0 = 0, good1 = 0, good2 = 0, good3 = 0;
+    uint64_t conf0 = 0, conf1 = 0, conf2 = 0, conf3 = 0;
+    for (uint32_t s = st.osum; s != 0; s &= s - 1) {
+        const int w = __builtin_ctz(s);
+        for (uint32_t cells = g.occ(w); cells != 0; cells &= cells - 1) {
+            const int p = (w << 5) | __builtin_ctz(cells);
+            const int fx = (p & (W - 1)) - bx.xmin, fy = (p >> Geometry<W>::kLogW) - bx.ymin;
+            const uint64_t bit = 1ull << (fy * 8 + fx);
+            shape |= bit;
+            const uint32_t id = (g.pend_word(p) >> ((uint32_t)(p & 7) * 4u)) & 15u;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
+                const int q = (p + delta) & kMask;
+                if (!g.occupied(q))
+                    continue;
+                const uint32_t nq = (g.pend_word(q) >> ((uint32_t)(q & 7) * 4u)) & 15u;
+                // options of the site in direction d + 2 of q's tile: cell p
+                const uint32_t opt = m.options(m.oriented((int)nq), (d + 2) & 3);
+                const bool good = opt != 0 && (opt >> 4) == 1u && (opt & 15u) == id;
+                const bool conf = opt != 0 && !good;
+                const uint64_t gb = good ? bit : 0ull, cb = conf ? bit : 0ull;
+                if (d == 0) { good0 |= gb; conf0 |= cb; }
+                else if (d == 1) { good1 |= gb; conf1 |= cb; }
+                else if (d == 2) { good2 |= gb; conf2 |= cb; }
+                else { good3 |= gb; conf3 |= cb; }
+            }
+        }
+    }
+    const int seed = (G / 2 - 1) * W + (G / 2 - 1);
+    const uint64_t seed_bit =
+        1ull << (((seed >> Geometry<W>::kLogW) - bx.ymin) * 8 + ((seed & (W - 1)) - bx.xmin));
+    // conflicts into the seed never count: the seed is placed first
+    uint64_t todo = (conf0 | conf1 | conf2 | conf3) & ~seed_bit;
+    bool guarded = true;
+    for (; todo != 0 && guarded; todo &= todo - 1) {
+        const uint64_t pb = todo & (~todo + 1);
+        // the conflicting neighbours of p: N is 8 bits down, S 8 up, E 1 up, W 1 down
+        const uint64_t src = ((conf0 & pb) >> 8) | ((conf2 & pb) << 8) | ((conf1 & pb) << 1) |
+                             ((conf3 & pb) >> 1);
+        const uint64_t allowed = shape & ~pb;
+        uint64_t reach = seed_bit, prev = 0;
+        while (reach != prev && (reach & src) == 0) {
+            prev = reach;
+            reach |= (((reach << 8) & good0) | ((reach >> 1) & good1) | ((reach >> 8) & good2) |
+                      ((reach << 1) & good3)) & allowed;
+        }
+        guarded = (reach & src) == 0;
+    }
+    return guarded;
+}
+
 // One-at-a-time hash of the cropped shape in orientation k of the dihedral
 // group: bit 2 transposes, bit 0 mirrors x, bit 1 mirrors y.  Cells are
 // listed in row-major order of the oriented frame, each as the bytes x, y

@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
             const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
             const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
                                         (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
-            forced = ev == kEvNone && shape_is_forced(src, g, st);
+            forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
         }
         const uint32_t h = det_hash(g, a, cache, forced, st.size, gd.grid);
         if (forced)
