@@ -52,13 +52,13 @@ def algorithmic_ops(n, steps, det_count, det_size):
     return OPS_GENOTYPE * n + OPS_PLACEMENT * steps + hash_ops(det_count, det_size)
 
 
-OPS_PROOF_CELL = 100.0   # forced-shape check: four neighbour lookups per cell
+OPS_PROOF_CELL = 100.0   # guarded-shape check: four neighbour lookups per cell
 
 
 def stage_ops(gold):
     """The same work split over the pipeline's kernels (per whole-space call):
     first runs (with the seed screen); the replayed first runs of the
-    candidates and the forced-shape check (forced candidates are final
+    candidates and the guarded-shape check (guarded candidates are final
     there); the repeat runs of the other candidates."""
     w = gold["work"]
     return {
@@ -66,7 +66,7 @@ def stage_ops(gold):
         + hash_ops(w["monomer_det"], w["monomer_det"])
         + OPS_PLACEMENT * w["run0_steps"] + hash_ops(w["run0_det"], w["run0_det_size"]),
         "prove_kernel<16>": OPS_PLACEMENT * w["cand_steps0"] + OPS_PROOF_CELL * w["cand_size"]
-        + hash_ops(w["forced"], w["forced_size"]),
+        + hash_ops(w["proven"], w["proven_size"]),
         "repeat_kernel<16>": OPS_PLACEMENT * w["unproven_steps"]
         + hash_ops(w["unproven_det"], w["unproven_det_size"]),
     }

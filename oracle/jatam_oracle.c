@@ -408,7 +408,8 @@ typedef struct {
     int steps;
     int event;
     int choice;
-    int forced;     /* the first run's shape is forced (forced_shape) */
+    int forced;     /* the first run's shape is forced (forced_shape)   */
+    int guarded;    /* the first run's shape is guarded (guarded_shape) */
 } run0_info_t;
 
 /* Whether the shape the run left in g is forced: for every occupied cell
@@ -443,6 +444,86 @@ static int forced_shape(const model_t* m, const grid_t* g)
     return 1;
 }
 
+/* The tiles that the tile at q admits at its neighbour p (direction d from
+ * p to q), as (count, one id) from options(): q shows its side facing p,
+ * the new tile at p faces back on side d. */
+static int options_from(const model_t* m, const grid_t* g, int q, int d, int* id)
+{
+    return options(m, m->tup[g->cell[q]][opposite(d)], d, id);
+}
+
+/* Whether target can be reached from the seed, in the shape the run left in
+ * g, by steps from an occupied cell a to an occupied neighbour b that a's
+ * tile admits exactly b's tile at (and nothing else), never entering cell x.
+ * Plain breadth-first search over the grid. */
+static int reached_without(const model_t* m, const grid_t* g, int x, int target)
+{
+    int W = g->W, seed = (g->G / 2) * W + g->G / 2;
+    static __thread int queue[MAXW * MAXW];
+    static __thread uint8_t seen[MAXW * MAXW];
+    if (seed == x)
+        return 0;
+    memset(seen, 0, sizeof(seen));
+    int head = 0, tail = 0;
+    queue[tail++] = seed;
+    seen[seed] = 1;
+    while (head < tail) {
+        int a = queue[head++];
+        if (a == target)
+            return 1;
+        int ax = a % W, ay = a / W;
+        for (int d = 0; d < 4; ++d) {
+            int bx = ax + DX[d], by = ay + DY[d];
+            if (bx < 0 || by < 0 || bx >= W || by >= W)
+                continue;
+            int b = by * W + bx;
+            if (b == x || seen[b] || g->cell[b] < 0)
+                continue;
+            int id = -1;
+            int k = options_from(m, g, a, opposite(d), &id);   /* a seen from b */
+            if (k != 1 || id != g->cell[b])
+                continue;
+            seen[b] = 1;
+            queue[tail++] = b;
+        }
+    }
+    return 0;
+}
+
+/* Whether the shape the run left in g (run ended with no event) is guarded:
+ * for every occupied cell p other than the seed and every occupied
+ * neighbour q whose tile admits at p anything but p's own tile, q cannot be
+ * reached from the seed by exact bonds without passing through p.  Then in
+ * every growth order q is placed after p, and every order places the same
+ * tiles in the same cells without events.  Forced shapes are the guarded
+ * shapes with no such pair.  (Not a step of the paper's method: an exact
+ * shortcut that a pipelined implementation may take, pinned by tests
+ * against the classification itself and against the brute-force
+ * explorer.) */
+static int guarded_shape(const model_t* m, const grid_t* g)
+{
+    int W = g->W, seed = (g->G / 2) * W + g->G / 2;
+    for (int p = 0; p < W * W; ++p) {
+        if (g->cell[p] < 0 || p == seed)
+            continue;
+        int px = p % W, py = p / W;
+        for (int d = 0; d < 4; ++d) {
+            int qx = px + DX[d], qy = py + DY[d];
+            if (qx < 0 || qy < 0 || qx >= W || qy >= W)
+                continue;
+            int q = qy * W + qx;
+            if (g->cell[q] < 0)
+                continue;
+            int id = -1;
+            int k = options_from(m, g, q, d, &id);
+            int conflict = k >= 2 || (k == 1 && id != g->cell[p]);
+            if (conflict && reached_without(m, g, p, q))
+                return 0;
+        }
+    }
+    return 1;
+}
+
 static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome,
                          uint64_t rng_id, int t, int c, int grid, int runs,
                          uint64_t seed, jref_result_t* out, uint8_t* occ_out,
@@ -464,6 +545,7 @@ static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome
             info0->event = ro.event;
             info0->choice = ro.choice;
             info0->forced = ro.event == EV_NONE && forced_shape(&m, g);
+            info0->guarded = ro.event == EV_NONE && guarded_shape(&m, g);
         }
         if (ro.event != EV_NONE) {
             out->cls = ro.event == EV_UNBOUND ? JREF_UNBOUND : JREF_ND_SITE;
@@ -589,7 +671,7 @@ static void* worker(void* arg)
             } else {
                 uint64_t g = job->mode == MODE_RANGE ? job->first + (uint64_t)i
                                                      : job->genomes[i];
-                run0_info_t info = { 0, 0, 0, 0 };
+                run0_info_t info = { 0, 0, 0, 0, 0 };
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, g,
                                    jref_default_rng_id(g, job->t), job->t, job->c,
                                    job->grid, job->runs, job->seed, &job->out[i], NULL,
@@ -598,7 +680,7 @@ static void* worker(void* arg)
                     job->run0_steps[i] = info.steps;
                     job->run0_event[i] = (int8_t)info.event;
                     job->run0_choice[i] = (int8_t)info.choice;
-                    job->run0_forced[i] = (int8_t)info.forced;
+                    job->run0_forced[i] = (int8_t)(info.forced | (info.guarded << 1));
                 }
             }
             if (rc != JREF_OK)

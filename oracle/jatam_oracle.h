@@ -99,9 +99,11 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
                         uint64_t seed, jref_result_t* out, int threads);
 
 /* Same as jref_classify_range, also reporting the first run of every
- * genotype: its placements, its event (0 none, 1 unbound, 2 ambiguous) and
- * whether it ever had two frontier sites to choose from.  Used to account
- * the work of each stage of a pipelined implementation. */
+ * genotype: its placements, its event (0 none, 1 unbound, 2 ambiguous),
+ * whether it ever had two frontier sites to choose from, and in
+ * run0_forced bit 0 whether its shape is forced, bit 1 whether it is
+ * guarded.  Used to account the work of each stage of a pipelined
+ * implementation and to pin the shortcuts such a pipeline takes. */
 int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
                              int runs, uint64_t seed, jref_result_t* out,
                              int32_t* run0_steps, int8_t* run0_event,

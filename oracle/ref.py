@@ -148,7 +148,8 @@ def classify_range(first: int, n: int, t: int, c: int = 8, grid: int = 16, runs:
 def classify_range_run0(first: int, n: int, t: int, c: int = 8, grid: int = 16,
                         runs: int = 20, seed: int = 1, threads: int = 0, forced: bool = False):
     """Records plus (steps, event, choice) of every genotype's first run, and
-    with forced=True also whether the first run's shape is forced."""
+    with forced=True also a flag per genotype: bit 0 set if the first run's
+    shape is forced, bit 1 set if it is guarded."""
     out = np.zeros(n, dtype=RECORD)
     s0 = np.zeros(n, dtype=np.int32)
     e0 = np.zeros(n, dtype=np.int8)

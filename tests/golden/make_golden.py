@@ -30,10 +30,12 @@ def slice_summary(recs, s0, e0, c0, f0, runs):
     # how the work splits over a pipeline: genotypes the seed alone decides
     # (0 placements) and first runs; then the candidates (first run drew a
     # random word and ended without an event): those whose first-run shape
-    # is forced are final after that run, the others need the repeat runs
+    # is guarded (forced shapes among them) are final after that run, the
+    # others need the repeat runs
     cand = (e0 == 0) & (c0 == 1) & (runs > 1)
-    forced = cand & (f0 == 1)
-    unproven = cand & (f0 == 0)
+    forced = cand & ((f0 & 1) != 0)
+    proven = cand & ((f0 & 2) != 0)
+    unproven = cand & ((f0 & 2) == 0)
     first_only = ~cand
     return {
         "sha256": hashlib.sha256(recs.tobytes()).hexdigest(),
@@ -50,6 +52,8 @@ def slice_summary(recs, s0, e0, c0, f0, runs):
             "cand_size": int(size[cand].sum()),
             "forced": int(forced.sum()),
             "forced_size": int(size[forced].sum()),
+            "proven": int(proven.sum()),
+            "proven_size": int(size[proven].sum()),
             "unproven": int(unproven.sum()),
             "unproven_steps": int(steps[unproven].sum()),
             "unproven_det": int(np.sum(det & unproven)),

@@ -447,7 +447,7 @@ def test_forced_shapes_classify_det_for_every_run_count(t, grid, space):
         for runs in (2, 7, 20):
             recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), n, t, grid=grid,
                                                            runs=runs, forced=True)
-            forced = f0 == 1
+            forced = (f0 & 1) != 0
             seen += int(np.sum(forced & (c0 == 1)))
             assert np.all(e0[forced] == 0)
             assert np.all(recs["cls"][forced] == ref.DET)
@@ -466,7 +466,7 @@ def test_forced_shapes_are_the_only_terminal_of_every_order():
     checked = 0
     for first in starts:
         recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), 4096, 2, forced=True)
-        for i in np.nonzero((f0 == 1) & (c0 == 1))[0][:12]:
+        for i in np.nonzero(((f0 & 1) != 0) & (c0 == 1))[0][:12]:
             g = int(first) + int(i)
             ex = bf.explore(g, 2, 8, 16, cap=20_000)
             if ex.capped:
@@ -477,3 +477,56 @@ def test_forced_shapes_are_the_only_terminal_of_every_order():
             assert len(shape) == recs["size"][i], g
             checked += 1
     assert checked >= 20
+
+
+# ---------------------------------------------------------------------------
+# Guarded shapes: a first-run shape in which, for every cell p other than the
+# seed and every occupied neighbour q whose tile admits at p something other
+# than p's tile, q cannot be reached from the seed over exact bonds without
+# passing through p.  Every forced shape is guarded.  Pinned like the forced
+# shapes: against the classification at several run counts (DET, first-run
+# size, (size - 1) * R placements) and against the brute-force explorer
+# (every growth order ends in the first run's shape, with no event).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t,grid,space", [(2, 16, 1 << 24), (3, 16, 1 << 36), (3, 32, 1 << 36),
+                                          (4, 10, 1 << 48)])
+def test_guarded_shapes_classify_det_for_every_run_count(t, grid, space):
+    rng = np.random.default_rng(t * 1000 + grid)
+    beyond_forced = 0
+    for first in rng.integers(0, space - 4096, size=3):
+        for runs in (2, 7, 20):
+            recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), 2048, t, grid=grid,
+                                                           runs=runs, forced=True)
+            forced = (f0 & 1) != 0
+            guarded = (f0 & 2) != 0
+            assert not np.any(forced & ~guarded)         # forced implies guarded
+            assert np.all(e0[guarded] == 0)
+            assert np.all(recs["cls"][guarded] == ref.DET)
+            placed = recs["size"][guarded].astype(np.int64) - 1
+            want = np.where(c0[guarded] == 1, placed * runs, placed)
+            assert np.array_equal(recs["steps"][guarded].astype(np.int64), want)
+            beyond_forced += int(np.sum(guarded & ~forced & (c0 == 1)))
+    assert beyond_forced > 0
+
+
+def test_guarded_shapes_are_the_only_terminal_of_every_order():
+    """Guarded genotypes of S_{2,8} and of the three-tile space that are not
+    forced (so a neighbour of some cell admits another tile there): the
+    brute-force explorer finds no event and exactly one terminal assembly,
+    the first run's shape."""
+    rng = np.random.default_rng(78)
+    checked = 0
+    for t, space in ((2, 1 << 24), (3, 1 << 36)):
+        for first in rng.integers(0, space - 4096, size=3):
+            recs, s0, e0, c0, f0 = ref.classify_range_run0(int(first), 4096, t, forced=True)
+            pick = np.nonzero(((f0 & 2) != 0) & ((f0 & 1) == 0) & (c0 == 1))[0]
+            for i in pick[:10]:
+                g = int(first) + int(i)
+                ex = bf.explore(g, t, 8, 16, cap=20_000)
+                if ex.capped:
+                    continue
+                assert not ex.events, (t, g)
+                assert len(ex.terminals) == 1, (t, g)
+                assert len(next(iter(ex.terminals))) == recs["size"][i], (t, g)
+                checked += 1
+    assert checked >= 30
