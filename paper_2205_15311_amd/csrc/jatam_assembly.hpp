@@ -386,9 +386,12 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
         const uint32_t p6 = p5 + __popc(f6), p7 = p6 + __popc(f7);
         if (p7 != st.nf)
             return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
-        const uint32_t wi = (uint32_t)(p0 <= j) + (uint32_t)(p1 <= j) + (uint32_t)(p2 <= j) +
-                            (uint32_t)(p3 <= j) + (uint32_t)(p4 <= j) + (uint32_t)(p5 <= j) +
-                            (uint32_t)(p6 <= j);
+        // p_k <= j exactly when p_k - (j + 1) is negative (all values < 2^9):
+        // sign bits summed, no compare-and-select chains
+        const uint32_t j1 = j + 1u;
+        const uint32_t wi = ((p0 - j1) >> 31) + ((p1 - j1) >> 31) + ((p2 - j1) >> 31) +
+                            ((p3 - j1) >> 31) + ((p4 - j1) >> 31) + ((p5 - j1) >> 31) +
+                            ((p6 - j1) >> 31);
         const bool b0 = (wi & 1u) != 0, b1 = (wi & 2u) != 0, b2 = (wi & 4u) != 0;
         const uint32_t fa = b0 ? f1 : f0, fb = b0 ? f3 : f2, fc = b0 ? f5 : f4, fd = b0 ? f7 : f6;
         const uint32_t ea = b0 ? p0 : 0u, eb = b0 ? p2 : p1, ec = b0 ? p4 : p3, ed = b0 ? p6 : p5;
@@ -440,7 +443,13 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
         if (!found)
             return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
     }
-    const int bit = select_bit(fw, j);
+    // the j-th set bit of the word: j is below the word's frontier count,
+    // nearly always 0..2, so clearing the lowest bit j times beats a
+    // fixed binary search
+    uint32_t rest = fw;
+    for (uint32_t k = 0; k < j; ++k)
+        rest &= rest - 1u;
+    const int bit = __builtin_ctz(rest);
     const int p = (w << 5) | bit;
     fw &= ~(1u << bit);
     g.fr(w) = fw;
