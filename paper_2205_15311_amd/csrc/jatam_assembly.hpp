@@ -72,23 +72,6 @@ struct LaneGrid {
 
 enum { kEvNone = 0, kEvUnbound = 1, kEvAmbig = 2, kEvCorrupt = 3 };
 
-// Position of the j-th (0-based) set bit of x, j < popcount(x).
-__device__ __forceinline__ int select_bit(uint32_t x, uint32_t j)
-{
-    int pos = 0;
-    uint32_t c = __popc(x & 0xFFFFu);
-    if (j >= c) { j -= c; x >>= 16; pos += 16; }
-    c = __popc(x & 0xFFu);
-    if (j >= c) { j -= c; x >>= 8; pos += 8; }
-    c = __popc(x & 0xFu);
-    if (j >= c) { j -= c; x >>= 4; pos += 4; }
-    c = __popc(x & 0x3u);
-    if (j >= c) { j -= c; x >>= 2; pos += 2; }
-    c = x & 1u;
-    if (j >= c) { pos += 1; }
-    return pos;
-}
-
 // Assembly state of one run, in registers.
 struct RunState {
     uint32_t nf;       // frontier size
