@@ -221,9 +221,18 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *   first_waves   persistent one-wave workgroups per CU of the first-run
  *                 stage, >= 1; capped at what fits in a CU (default: that)
  *   repeat_waves  the same for the repeat stage
- *   wide_layout   G <= 16 class only: 1 classifies these genotypes with the
+ *   wide_layout   G <= 16 class: 1 classifies these genotypes with the
  *                 32 x 32 LDS layout (and the other class's parameters)
- *                 instead of the 16 x 16 one (default 0)
+ *                 instead of the 16 x 16 one (default 0).
+ *                 16 < G <= 32 class: 2 first classifies these genotypes
+ *                 in a 16 x 16 window around the seed, with the G <= 16
+ *                 class's parameters, and reruns in 32 x 32 grids (with
+ *                 this class's parameters) only those whose record came out
+ *                 UNBOUND there, since only a run that reaches the window's
+ *                 ring can differ from the run in its own grid; 1 classifies
+ *                 them in 32 x 32 grids directly; 0 (default) is 2 for calls
+ *                 of at least 2^20 genotypes and 1 below.  The G <= 16
+ *                 class at 1 turns the window off.
  */
 typedef struct {
     int refill;

@@ -176,13 +176,24 @@ static int next_marks(jatam_batch_t* b, hipEvent_t** marks, uint8_t** launched)
 
 // Launches the pipeline.  grid_limit: the uniform G of the call, or 0 for
 // mixed items (both grid classes).  marks/launched: timing hook or nullptr.
+// Calls from this many items up take the 16 x 16 window for 16 < G <= 32 by
+// default.  On smaller calls the window's extra stages and the reruns of the
+// items that leave it (populations of large shapes) cost more than it saves.
+constexpr int64_t kWindowMinItems = 1 << 20;
+
 static int launch_pipeline(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
                            hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
 {
     const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
-    a.narrow_max = b->tune[0].wide_layout ? 0 : 16;
+    // G <= narrow_max runs in the 16 x 16 layout; with the window on (the
+    // default) that is every G <= 32, and the 32 x 32 class reruns only the
+    // items of G > 16 that left the window
+    const int w1 = b->tune[1].wide_layout;
+    const bool window =
+        !b->tune[0].wide_layout && (w1 == 2 || (w1 == 0 && a.n >= kWindowMinItems));
+    a.narrow_max = b->tune[0].wide_layout ? 0 : window ? 32 : 16;
     const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
-                             grid_limit == 0 || grid_limit > a.narrow_max};
+                             grid_limit == 0 || grid_limit > (window ? 16 : a.narrow_max)};
     jatam::StageLaunch launch[2];
     for (int k = 0; k < 2; ++k) {
         const jatam_tuning_t& t = b->tune[k];
@@ -277,6 +288,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
              batch_alloc(b, staging * sizeof(uint16_t), (void**)&ws.cand_size[k]) &&
              batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.sorted[k]);
     }
+    ok = ok && batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.overflow);
     if (!ok) {
         free_batch(b);
         return JATAM_E_HIP;
@@ -332,6 +344,7 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.slice = nullptr;
     a.out_per_slice = 0;
     a.narrow_max = 16;
+    a.n_dev = nullptr;
     a.refill = 24;
     a.seg_cap = 0;
     a.out = out;
@@ -499,8 +512,8 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
 {
     if (batch == nullptr || tuning == nullptr || grid_limit < 8 || grid_limit > 32 ||
         tuning->refill < 1 || tuning->refill > 64 || tuning->first_waves < 1 ||
-        tuning->repeat_waves < 1 || tuning->wide_layout < 0 || tuning->wide_layout > 1 ||
-        (grid_limit > 16 && tuning->wide_layout != 0))
+        tuning->repeat_waves < 1 || tuning->wide_layout < 0 ||
+        tuning->wide_layout > (grid_limit > 16 ? 2 : 1))
         return JATAM_E_INVALID_ARG;
     batch->tune[grid_limit <= 16 ? 0 : 1] = *tuning;
     return JATAM_OK;
@@ -574,6 +587,8 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
             choices = wave_choices(batch->occ[k][ti][1]);
         else if (k == 0)
             choices = {0, 1};
+        else
+            choices = {0, 1, 2};
         for (int v : choices) {
             jatam_tuning_t trial = cur;
             int* slot = field == 0 ? &trial.refill : field == 1 ? &trial.first_waves

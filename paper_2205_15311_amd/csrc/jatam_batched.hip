@@ -71,6 +71,22 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint64_t first, u
     return g;
 }
 
+// The genotype as the kernels of a grid class run it: in the 16 x 16 layout
+// an item of G > 16 runs in a window of G = 16 around the seed.  Up to the
+// first placement that exposes a bondable site on the window's ring, such a
+// run is the run in its own G x G grid (same cells relative to the seed,
+// same row-major order, same draws); a run that reaches the window's ring
+// ends UNBOUND here and the item is run again in its own grid (see
+// overflow_count_kernel).
+template <int W>
+__device__ __forceinline__ Geno run_geno(const BatchArgs& a, uint64_t first, uint32_t i)
+{
+    Geno g = fetch_geno(a, first, i);
+    if constexpr (W == 16)
+        g.grid = g.grid < 16 ? g.grid : 16;
+    return g;
+}
+
 // A graph-replayed enumeration reads its slice s from the device: the call
 // covers genotypes first + s*n .. and writes records at out + s*n if asked.
 // (The kernel argument block is left untouched: a modified copy would live
@@ -187,7 +203,8 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     dc.reset();
 
     const uint32_t wave = blockIdx.x, nwaves = gridDim.x;
-    const uint32_t nchunks = (uint32_t)((a.n + 63) / 64);
+    const uint32_t n_items = a.n_dev != nullptr ? *a.n_dev : (uint32_t)a.n;
+    const uint32_t nchunks = (n_items + 63) / 64;
     uint32_t next_chunk = wave;               // this wave owns chunks wave + k*nwaves
     uint32_t head = 0, queued = 0;            // survivor ring (wave-uniform)
     uint32_t staged = 0;                      // candidates in this wave's segment
@@ -210,7 +227,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 // screen one chunk of the input (§3.2: what the seed decides)
                 const uint32_t pos = next_chunk * 64 + (uint32_t)lane_id();
                 uint32_t i = pos;
-                bool in_range = pos < (uint64_t)a.n;
+                bool in_range = pos < n_items;
                 if (in_range && a.order != nullptr) {
                     i = a.order[pos];
                     in_range = i < (uint64_t)a.n;   // an entry out of range is skipped
@@ -221,8 +238,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 if (in_range) {
                     const Geno s = fetch_geno(a, first, i);
                     if (!s.valid) {
-                        // exactly one launched pass reports an invalid item
-                        if (grid_class(a, s.grid) == klass)
+                        // exactly one launched pass reports an invalid item:
+                        // its grid's class, or with the window on (the
+                        // 32 x 32 class then reruns listed items only) the
+                        // 16 x 16 class
+                        if (a.narrow_max > 16 ? klass == 0 : grid_class(a, s.grid) == klass)
                             out[i] = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
                     } else if (grid_class(a, s.grid) == klass) {
                         const Model<TM> sm = build_model<TM>(s.genome, s.t, a.bits, a.c);
@@ -265,7 +285,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 if (rank < take) {
                     const uint32_t slot = (head + rank) % kRing;
                     idx = ring[slot];
-                    gd = fetch_geno(a, first, idx);
+                    gd = run_geno<W>(a, first, idx);
                     m.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                     ev = run_start_known(g, st, dc, gd.grid, ring_opt[slot]);
                     busy = true;
@@ -501,7 +521,7 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
         Geno gd{0, 0, 0, 0, false};
         if (active) {
             idx = queue[pos];
-            gd = fetch_geno(a, first, idx);
+            gd = run_geno<W>(a, first, idx);
             const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
             const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
                                         (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
@@ -544,6 +564,62 @@ __global__ __launch_bounds__(256) void compact_kernel(const BatchArgs a, int kla
     if (kept) {
         const uint32_t base = a.ws.chunk_cnt[klass][c] + a.ws.chunk_sums[klass][c / kScanBlock];
         a.ws.sorted[klass][base + (uint32_t)__popcll(m & lanes_below())] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The 16 x 16 window (items of G > 16 classified in the 16 x 16 layout, see
+// run_geno).  An item whose record came out UNBOUND there exposed a bondable
+// site on the window's ring in some run up to the deciding one; every other
+// item's record is exact: no run up to the deciding one left the window, so
+// those runs equal the runs in the item's own grid.  The items that left are
+// listed, in queue order, for a rerun of the pipeline in 32 x 32 grids: one
+// wave per chunk of 64 queue positions counts them, a scan places them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool left_window(const BatchArgs& a, uint64_t first,
+                                            const jatam_result_t* out, uint32_t pos,
+                                            uint32_t& i)
+{
+    i = pos;
+    if (pos >= (uint64_t)a.n)
+        return false;
+    if (a.order != nullptr) {
+        i = a.order[pos];
+        if (i >= (uint64_t)a.n)
+            return false;
+    }
+    const Geno s = fetch_geno(a, first, i);
+    return s.valid && s.grid > 16 && grid_class(a, s.grid) == 0 && out[i].cls == JATAM_UNBOUND;
+}
+
+__global__ __launch_bounds__(256) void overflow_count_kernel(const BatchArgs a)
+{
+    const uint32_t c = blockIdx.x * 4 + threadIdx.x / 64;   // one chunk per wave
+    if (c >= (uint32_t)((a.n + 63) / 64))
+        return;
+    uint32_t i;
+    const bool left = left_window(a, slice_first(a), slice_out(a), c * 64 + (uint32_t)lane_id(), i);
+    const uint64_t m = __ballot(left);
+    if (lane_id() == 0)
+        a.ws.chunk_cnt[1][c] = (uint32_t)__popcll(m);
+}
+
+__global__ __launch_bounds__(256) void overflow_scatter_kernel(const BatchArgs a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.tally != nullptr) {
+        // the window pass counted these items UNBOUND; the rerun counts them
+        atomicAdd(&a.tally[JATAM_UNBOUND],
+                  0ull - (unsigned long long)a.ws.counters[kCntOverflow]);
+    }
+    const uint32_t c = blockIdx.x * 4 + threadIdx.x / 64;
+    if (c >= (uint32_t)((a.n + 63) / 64))
+        return;
+    uint32_t i;
+    const bool left = left_window(a, slice_first(a), slice_out(a), c * 64 + (uint32_t)lane_id(), i);
+    const uint64_t m = __ballot(left);
+    if (left) {
+        const uint32_t base = a.ws.chunk_cnt[1][c] + a.ws.chunk_sums[1][c / kScanBlock];
+        a.ws.overflow[base + (uint32_t)__popcll(m & lanes_below())] = i;
     }
 }
 
@@ -607,7 +683,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             // lane j of the group), shared through the orientation slots
             TableSource<TM> src;
             if (active) {
-                gd = fetch_geno(a, first, idx);
+                gd = run_geno<W>(a, first, idx);
                 src.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                 for (int j = run; j < 8; j += R)
                     orient[j][grp] = bond_table_word(src.m, j);
@@ -622,7 +698,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             }
         } else {
             if (active) {
-                gd = fetch_geno(a, first, idx);
+                gd = run_geno<W>(a, first, idx);
                 const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
                 ev = run_assembly(src, g, st, gd.grid, run, a.key0, a.key1, (uint32_t)gd.rng_id,
                                   (uint32_t)(gd.rng_id >> 32));
@@ -808,6 +884,17 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
         a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64);
         begin(kStageFirst + kStagesPerClass * k);
+        if (k == 1 && a.narrow_max > 16) {
+            // the 32 x 32 class reruns only the items that left the window
+            const uint32_t blocks = (uint32_t)((nchunks + 3) / 4);
+            hipLaunchKernelGGL(overflow_count_kernel, dim3(blocks), dim3(256), 0, stream, a);
+            exclusive_scan(a.ws.chunk_cnt[1], (uint32_t)nchunks, a.ws.chunk_sums[1],
+                           a.ws.counters + kCntOverflow, stream);
+            hipLaunchKernelGGL(overflow_scatter_kernel, dim3(blocks), dim3(256), 0, stream, a);
+            a.order = a.ws.overflow;
+            a.n_dev = a.ws.counters + kCntOverflow;
+            a.narrow_max = 16;
+        }
         if (k == 0)
             hipLaunchKernelGGL((first_run_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
         else

@@ -32,6 +32,7 @@ enum {
     kCntDiff = 2,     // record comparison flag of the autotuner
     kCntSlice = 3,    // slice counter of a graph-replayed enumeration
     kCntCandAll = 4,  // [2] candidates before the forced-shape proof
+    kCntOverflow = 6, // items that left the 16 x 16 window (rerun in 32 x 32 grids)
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
@@ -50,6 +51,7 @@ struct DeviceWorkspace {
     uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks + 1)] per-wave segments
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
+    uint32_t* overflow;       // [max_n] items to rerun in 32 x 32 grids
     uint32_t* small_hash;     // [2]: D4 hash of the monomer and of the domino
     jatam_result_t* records;  // [max_n] records of a GA generation
 };
@@ -66,7 +68,11 @@ struct BatchArgs {
     const uint32_t* slice;          // nullptr, or device slice counter s: the call
                                     // covers first + s*n .. (graph replays)
     int out_per_slice;              // with `slice`: records go to out + s*n
-    int narrow_max;                 // largest G classified with the 16 x 16 layout
+    int narrow_max;                 // largest G classified with the 16 x 16 layout;
+                                    // above 16 the layout is a window (see
+                                    // overflow_count_kernel)
+    const uint32_t* n_dev;          // nullptr, or the item count on the device
+                                    // (first-run stage; at most n)
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
     jatam_result_t* out;

@@ -65,6 +65,8 @@ def test_autotune_on_s28_keeps_the_golden_records(jt):
     (16, dict(refill=64, first_waves=3, repeat_waves=2)),
     (16, dict(wide_layout=1)),
     (32, dict(refill=8, first_waves=1, repeat_waves=2)),
+    (32, dict(wide_layout=1)),
+    (32, dict(wide_layout=2)),
 ])
 def test_explicit_tunings_keep_records(jt, grid, tuning):
     rng = np.random.default_rng(grid + len(tuning))
@@ -82,7 +84,9 @@ def test_bad_tunings_rejected(jt):
             with pytest.raises(jt.JatamError):
                 b.set_tuning(16, **bad)
         with pytest.raises(jt.JatamError):
-            b.set_tuning(32, wide_layout=1)
+            b.set_tuning(32, wide_layout=3)
+        with pytest.raises(jt.JatamError):
+            b.set_tuning(16, wide_layout=2)
 
 
 def mixed_items(jt, n):
@@ -125,3 +129,21 @@ def test_surrogate_cost_order_keeps_records(jt):
         dev = torch.from_numpy(jt.make_items(g, t, grid)).cuda()
         got = records(b.classify_items(dev, 8, 20, 1, order=order))
     assert_same(got, ref.classify_items(items), "surrogate order")
+
+
+@pytest.mark.parametrize("t,grid", [(3, 32), (2, 32), (3, 24), (4, 20)])
+def test_window_and_direct_wide_layout_agree(jt, t, grid):
+    """16 < G <= 32: the 16 x 16 window with a 32 x 32 rerun of the items
+    that left it, the direct 32 x 32 classification, and the default (direct
+    at this call size) give the oracle's records and tallies."""
+    rng = np.random.default_rng(40 + t + grid)
+    g = rng.integers(0, 1 << (12 * t), size=40_000, dtype=np.uint64)
+    want = ref.classify(g, t, grid=grid, runs=20, seed=1)
+    dev = torch.from_numpy(g.view(np.int64)).cuda()
+    with jt.Batch(1 << 16) as b:
+        for wide in (2, 1, 0):
+            b.set_tuning(32, wide_layout=wide)
+            tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+            got = records(b.classify(dev, t, 8, grid, 20, 1, tally=tally))
+            assert_same(got, want, f"t={t} G={grid} wide_layout={wide}")
+            assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
