@@ -530,3 +530,23 @@ def test_guarded_shapes_are_the_only_terminal_of_every_order():
                 assert len(next(iter(ex.terminals))) == recs["size"][i], (t, g)
                 checked += 1
     assert checked >= 30
+
+
+# ---------------------------------------------------------------------------
+# The 16 x 16 window: a genotype classified with G = 16 gets the record of its
+# own G > 16 unless that record is UNBOUND (no run up to the deciding one
+# reached the window's ring, and such runs are the runs in the larger grid).
+# A pipeline may classify G > 16 in the window and rerun only the UNBOUND
+# ones; pinned here on the oracle for t = 2..4 and G = 18..32.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("t,grid", [(2, 32), (3, 32), (3, 20), (4, 24), (2, 18)])
+def test_window_records_equal_unless_unbound(t, grid):
+    rng = np.random.default_rng(500 + 10 * t + grid)
+    g = rng.integers(0, 1 << (12 * t), size=4000, dtype=np.uint64)
+    small = ref.classify(g, t, grid=16)
+    big = ref.classify(g, t, grid=grid)
+    inside = small["cls"] != ref.UNBOUND
+    assert np.array_equal(small[inside], big[inside])
+    # and the window is not vacuous: some records differ, all of them UNBOUND at 16
+    assert np.any(~inside)
+    assert np.all(small["cls"][small != big] == ref.UNBOUND)
