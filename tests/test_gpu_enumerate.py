@@ -101,3 +101,27 @@ def test_enumerate_argument_errors(jt):
         bad = torch.zeros((100, 2), dtype=torch.int64, device="cuda")
         with pytest.raises(jt.JatamError):
             b.enumerate(0, 1024, 1, 2, 8, 16, 20, 1, shapes=bad)
+
+
+def test_window_in_graph_replays(jt):
+    """Three-tile slices at G = 32 through the 16 x 16 window (forced on),
+    the list of items that left it and their 32 x 32 rerun all inside the
+    captured slice pipeline: records, tally and shape histogram equal the
+    oracle's, and some items did leave the window."""
+    first, n, k = 8_592_194_344, 1 << 15, 4
+    want = ref.classify_range(first, k * n, 3, grid=32)
+    assert np.sum(want["cls"] == ref.UNBOUND) > 100
+    out = torch.empty((k * n, 4), dtype=torch.int32, device="cuda")
+    tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+    table = torch.zeros((1024, 2), dtype=torch.int64, device="cuda")
+    with jt.Batch(n) as b:
+        b.set_tuning(32, wide_layout=2)
+        b.enumerate(first, n, k, 3, 8, 32, 20, 1, out=out, tally=tally, shapes=table)
+        torch.cuda.synchronize()
+        rec = out.cpu().numpy().view(ref.RECORD).reshape(-1)
+    assert np.array_equal(rec, want)
+    assert tally.cpu().tolist() == [int(np.sum(want["cls"] == c)) for c in range(4)]
+    det = want[want["cls"] == ref.DET]
+    keys, counts = np.unique(np.stack([det["size"].astype(np.int64), det["hash"].astype(np.int64)]),
+                             axis=1, return_counts=True)
+    assert shapes_of(jt, table) == [(int(h), int(z), int(c)) for (z, h), c in zip(keys.T, counts)]
