@@ -251,8 +251,9 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
  * jatam_batch_classify_range, 1 <= n <= the workspace's max_n).  Starting
  * from the current parameters it tries, one field at a time, refill in
  * {8, 16, 24, 32, 48}, first_waves and repeat_waves at and below the
- * residency limit, and (G <= 16) both layouts, keeping a value when the
- * median of three timed calls improves.  Every candidate's records are
+ * residency limit, and every wide_layout value of the class, keeping a
+ * value when the median of three timed calls improves by more than 1%
+ * (less is within run-to-run noise).  Every candidate's records are
  * compared with the starting configuration's, bit for bit: a difference
  * stops the search with JATAM_E_MISMATCH.  The best parameters found are
  * set on the workspace and written to *best (if not NULL).

@@ -607,7 +607,8 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
                 break;
             }
             batch->tune_log.push_back({trial, ms});
-            if (ms < cur_ms) {
+            // a change must win by more than the run-to-run noise
+            if (ms < 0.99 * cur_ms) {
                 cur = trial;
                 cur_ms = ms;
             }
