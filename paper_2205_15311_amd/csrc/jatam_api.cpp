@@ -67,7 +67,7 @@ int make_params(int t, int c, int grid, int runs, uint64_t seed, jatam::Params* 
 std::vector<int> wave_choices(int occ)
 {
     std::vector<int> v;
-    for (int w : {occ, occ - 1, occ - 2, (occ + 1) / 2})
+    for (int w : {occ, occ - 1, occ - 2, (occ + 1) / 2, (occ + 3) / 4})
         if (w >= 1 && std::find(v.begin(), v.end(), w) == v.end())
             v.push_back(w);
     return v;
