@@ -15,6 +15,7 @@ struct jatam_batch {
     int cus;                       // compute units of the device
     int occ[2][2][2];              // resident blocks per CU [class][tile bound][stage]
     jatam_tuning_t tune[2];        // launch parameters per grid class
+    uint32_t small_hash[2];        // host copy of the workspace's small_hash
     std::vector<std::pair<jatam_tuning_t, double>> tune_log;   // last autotune
     jatam::DeviceWorkspace ws;
     void* allocations[24];
@@ -294,7 +295,9 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
         return JATAM_E_HIP;
     }
     if (jatam::batch_init_small_hash(ws.small_hash, nullptr) != JATAM_OK ||
-        hipDeviceSynchronize() != hipSuccess) {
+        hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(b->small_hash, ws.small_hash, sizeof(b->small_hash), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
         free_batch(b);
         return JATAM_E_HIP;
     }
@@ -347,6 +350,8 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.n_dev = nullptr;
     a.refill = 24;
     a.seg_cap = 0;
+    a.small0 = b->small_hash[0];
+    a.small1 = b->small_hash[1];
     a.out = out;
     a.tally = reinterpret_cast<unsigned long long*>(tally);
     a.ws = b->ws;

@@ -72,6 +72,18 @@ struct LaneGrid {
 
 enum { kEvNone = 0, kEvUnbound = 1, kEvAmbig = 2, kEvCorrupt = 3 };
 
+// For one-wave workgroups: LDS writes made by the wave before this point are
+// seen by its LDS reads after it.  A wave's LDS operations are performed in
+// order, so only the compiler must not move accesses across the point: no
+// s_barrier, and no wait for the wave's outstanding global stores, which the
+// workgroup-scope fence of __syncthreads adds.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Assembly state of one run, in registers.
 struct RunState {
     uint32_t nf;       // frontier size
@@ -843,9 +855,9 @@ struct ShapeCache {
         hash = v.z;
         return v.x == (uint32_t)m && v.y == (uint32_t)(m >> 32);
     }
-    // Called by the whole wave: every lane with `want` stores its entry, in
-    // lane order (a later lane with the same slot overwrites), then the
-    // wave's LDS writes are complete before any later lookup.
+    // Called by the whole wave of a one-wave workgroup: every lane with
+    // `want` stores its entry, in lane order (a later lane with the same
+    // slot overwrites), then the wave's later lookups see the entries.
     __device__ __forceinline__ void insert(bool want, uint64_t m, uint32_t hash, int lane)
     {
         uint64_t pending = __ballot(want);
@@ -855,7 +867,7 @@ struct ShapeCache {
             if (lane == __builtin_ctzll(pending))
                 e[slot(m)] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), hash, 0u);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 };
 

@@ -71,6 +71,40 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint64_t first, u
     return g;
 }
 
+// Input modes, as a compile-time choice for the first-run kernel: a range
+// (genome = first + i, no loads), a genome list, or items.  With the mode
+// fixed, a range call has no global loads in its loop, and so no waits
+// (the vector memory counter also counts the loop's record stores).
+enum { kInRange = 0, kInList = 1, kInItems = 2, kInRuntime = 3 };
+
+template <int kIn>
+__device__ __forceinline__ Geno fetch_geno_in(const BatchArgs& a, uint64_t first, uint32_t i)
+{
+    if constexpr (kIn == kInRuntime) {
+        return fetch_geno(a, first, i);
+    } else if constexpr (kIn == kInItems) {
+        Geno g;
+        const jatam_item_t it = a.items[i];
+        g.genome = it.genome;
+        g.rng_id = it.rng_id;
+        g.t = it.t;
+        g.grid = it.grid;
+        const int gbits = 4 * g.t * a.bits;
+        g.valid = g.t >= 1 && g.t <= 4 && gbits <= 64 && g.grid >= 8 && g.grid <= 32 &&
+                  (g.grid & 1) == 0 && (gbits == 64 || (g.genome >> gbits) == 0);
+        return g;
+    } else {
+        Geno g;
+        g.genome = kIn == kInList ? a.genomes[i] : first + (uint64_t)i;
+        g.t = a.t;
+        g.grid = a.grid;
+        g.rng_id = g.genome | ((uint64_t)(uint32_t)a.t << 56);
+        const int gbits = 4 * a.t * a.bits;
+        g.valid = gbits == 64 || (g.genome >> gbits) == 0;
+        return g;
+    }
+}
+
 // The genotype as the kernels of a grid class run it: in the 16 x 16 layout
 // an item of G > 16 runs in a window of G = 16 around the seed.  Up to the
 // first placement that exposes a bondable site on the window's ring, such a
@@ -78,10 +112,10 @@ __device__ __forceinline__ Geno fetch_geno(const BatchArgs& a, uint64_t first, u
 // same row-major order, same draws); a run that reaches the window's ring
 // ends UNBOUND here and the item is run again in its own grid (see
 // overflow_count_kernel).
-template <int W>
+template <int W, int kIn = kInRuntime>
 __device__ __forceinline__ Geno run_geno(const BatchArgs& a, uint64_t first, uint32_t i)
 {
-    Geno g = fetch_geno(a, first, i);
+    Geno g = fetch_geno_in<kIn>(a, first, i);
     if constexpr (W == 16)
         g.grid = g.grid < 16 ? g.grid : 16;
     return g;
@@ -155,8 +189,10 @@ using WaveShapeCache = ShapeCache<kShapeCache>;
 // their hashes are computed once per workspace (small_hash_kernel).  Shapes
 // that fit 8 x 8 go through the wave's cache; a miss hashes the bitmap and
 // fills the cache.
+// small0/small1: the monomer's and the domino's hashes, read once per kernel
+// (a load in the loop would make the wave wait for all its record stores).
 template <int W>
-__device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs& a,
+__device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, uint32_t small0, uint32_t small1,
                                              WaveShapeCache& cache, bool want, int size, int grid)
 {
     uint32_t h = 0;
@@ -164,7 +200,7 @@ __device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs
     uint64_t key = 0;
     if (want) {
         if (size <= 2) {
-            h = a.ws.small_hash[size - 1];
+            h = size <= 1 ? small0 : small1;
         } else if (shape_key8(g, grid, key)) {
             if (!cache.lookup(key, h)) {
                 h = bitmap8_shape_hash(key);
@@ -183,9 +219,10 @@ __device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, const BatchArgs
 // ---------------------------------------------------------------------------
 constexpr int kRing = 128;   // LDS survivor ring per wave (>= 2 chunks)
 
-template <int W, int TM>
+template <int W, int TM, int kIn>
 __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int klass)
 {
+    const uint32_t small0 = a.small0, small1 = a.small1;
     using Geo = Geometry<W>;
     const uint64_t first = slice_first(a);
     jatam_result_t* const out = slice_out(a);
@@ -236,7 +273,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 int cls = 0;
                 uint32_t opts = 0;
                 if (in_range) {
-                    const Geno s = fetch_geno(a, first, i);
+                    const Geno s = fetch_geno_in<kIn>(a, first, i);
                     if (!s.valid) {
                         // exactly one launched pass reports an invalid item:
                         // its grid's class, or with the window on (the
@@ -260,7 +297,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                             done = true;
                             cls = JATAM_ND_SITE;
                         } else if (!bonds) {
-                            out[i] = jatam_result_t{JATAM_DET, 1, a.ws.small_hash[0], 0};
+                            out[i] = jatam_result_t{JATAM_DET, 1, small0, 0};
                             done = true;
                             cls = JATAM_DET;
                         } else {
@@ -278,14 +315,14 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 queued += (uint32_t)__popcll(km);
                 next_chunk += nwaves;
             }
-            __syncthreads();   // ring writes visible to the whole wave
+            wave_lds_sync();   // ring writes visible to the whole wave
             const uint32_t take = queued < nidle ? queued : nidle;
             if (!busy) {
                 const uint32_t rank = (uint32_t)__popcll(idle & lanes_below());
                 if (rank < take) {
                     const uint32_t slot = (head + rank) % kRing;
                     idx = ring[slot];
-                    gd = run_geno<W>(a, first, idx);
+                    gd = run_geno<W, kIn>(a, first, idx);
                     m.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
                     ev = run_start_known(g, st, dc, gd.grid, ring_opt[slot]);
                     busy = true;
@@ -293,7 +330,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
             }
             head = (head + take) % kRing;
             queued -= take;
-            __syncthreads();   // ring slots read before they are refilled
+            wave_lds_sync();   // ring slots read before they are refilled
         }
         if (__ballot(busy) == 0) {
             if (queued == 0 && next_chunk >= nchunks)
@@ -331,7 +368,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
             }
         }
         if (__ballot(det) != 0)
-            rec.hash = det_hash(g, a, cache, det, st.size, gd.grid);
+            rec.hash = det_hash(g, small0, small1, cache, det, st.size, gd.grid);
         if (finish) {
             if (done)
                 out[idx] = rec;
@@ -496,6 +533,7 @@ constexpr uint32_t kNoCandidate = 0xFFFFFFFFu;
 template <int W, int TM>
 __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
 {
+    const uint32_t small0 = a.small0, small1 = a.small1;
     using Geo = Geometry<W>;
     const uint64_t first = slice_first(a);
     jatam_result_t* const out = slice_out(a);
@@ -527,7 +565,7 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
                                         (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
             forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
         }
-        const uint32_t h = det_hash(g, a, cache, forced, st.size, gd.grid);
+        const uint32_t h = det_hash(g, small0, small1, cache, forced, st.size, gd.grid);
         if (forced)
             out[idx] = jatam_result_t{JATAM_DET, st.size, h, (st.size - 1) * a.runs};
         tally.add(forced, JATAM_DET);
@@ -762,7 +800,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             jatam_result_t rec;
             if (det) {
                 if (size0 <= 2) {
-                    h = a.ws.small_hash[size0 - 1];
+                    h = size0 <= 1 ? a.small0 : a.small1;
                 } else if (hit) {
                     h = cached;
                 } else {
@@ -816,7 +854,8 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream)
 template <int W, int TM>
 static void occupancy_of(int out[2])
 {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[0], first_run_kernel<W, TM>, 64, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[0], first_run_kernel<W, TM, kInRange>,
+                                                     64, 0) !=
             hipSuccess ||
         out[0] < 1)
         out[0] = 1;
@@ -861,6 +900,21 @@ int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
+// The first-run kernel compiled for the call's input mode.
+template <int W, int TM>
+static void launch_first(const BatchArgs& a, uint32_t nb, hipStream_t stream, int klass)
+{
+    if (a.items != nullptr)
+        hipLaunchKernelGGL((first_run_kernel<W, TM, kInItems>), dim3(nb), dim3(64), 0, stream, a,
+                           klass);
+    else if (a.genomes != nullptr)
+        hipLaunchKernelGGL((first_run_kernel<W, TM, kInList>), dim3(nb), dim3(64), 0, stream, a,
+                           klass);
+    else
+        hipLaunchKernelGGL((first_run_kernel<W, TM, kInRange>), dim3(nb), dim3(64), 0, stream, a,
+                           klass);
+}
+
 template <int TM>
 static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch launch[2],
                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
@@ -896,9 +950,9 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             a.narrow_max = 16;
         }
         if (k == 0)
-            hipLaunchKernelGGL((first_run_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
+            launch_first<16, TM>(a, nb, stream, 0);
         else
-            hipLaunchKernelGGL((first_run_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
+            launch_first<32, TM>(a, nb, stream, 1);
         end(kStageFirst + kStagesPerClass * k);
         begin(kStageSort + kStagesPerClass * k);
         hipLaunchKernelGGL(sort_hist_kernel, dim3(nb), dim3(256), 0, stream, a, k);

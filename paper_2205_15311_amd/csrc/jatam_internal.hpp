@@ -75,6 +75,8 @@ struct BatchArgs {
                                     // (first-run stage; at most n)
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
+    uint32_t small0, small1;        // D4 hashes of the monomer and the domino (the
+                                    // workspace's small_hash, copied at creation)
     jatam_result_t* out;
     unsigned long long* tally;      // nullptr or [4], accumulated
     DeviceWorkspace ws;
