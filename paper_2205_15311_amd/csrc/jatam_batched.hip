@@ -726,7 +726,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
                 for (int j = run; j < 8; j += R)
                     orient[j][grp] = bond_table_word(src.m, j);
             }
-            __syncthreads();
+            wave_lds_sync();
             if (active) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d)
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
                                   (uint32_t)(gd.rng_id >> 32));
             }
         }
-        __syncthreads();   // every run's grid is final (and the table slots read)
+        wave_lds_sync();   // every run's grid is final (and the table slots read)
         // a witness is a later run that hit an event or ended in another shape
         bool same = true;
         if (active && run > 0 && ev == kEvNone) {
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         const bool done = active && run == 0;
         uint32_t h = 0;
         if (done) {
@@ -820,7 +820,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
         }
         tally.add(done, cls);
         cache.insert(done && det && small && !hit, key, h, lane);
-        __syncthreads();   // orientation slots and grids reused next round
+        wave_lds_sync();   // orientation slots and grids reused next round
     }
     tally.flush(a.tally);
 }
