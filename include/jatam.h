@@ -233,12 +233,20 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *                 them in 32 x 32 grids directly; 0 (default) is 2 for calls
  *                 of at least 2^20 genotypes and 1 below.  The G <= 16
  *                 class at 1 turns the window off.
+ *   claim_share   first runs: sixteenths of the input's 64-item chunks that
+ *                 waves claim from a device counter, four chunks at a time,
+ *                 once their dealt-out chunks are done (0..16; default 8).
+ *                 The rest are dealt out in turn (chunk k to wave k mod the
+ *                 grid).  Run lengths follow the genome's digits, so dealt-
+ *                 out chunks leave some waves far more work than others;
+ *                 claimed chunks go to the waves that finish first.
  */
 typedef struct {
     int refill;
     int first_waves;
     int repeat_waves;
     int wide_layout;
+    int claim_share;
 } jatam_tuning_t;
 
 /* The parameters used for grid_limit's class (8 <= grid_limit <= 32). */
@@ -251,7 +259,8 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
  * jatam_batch_classify_range, 1 <= n <= the workspace's max_n).  Starting
  * from the current parameters it tries, one field at a time, refill in
  * {8, 16, 24, 32, 48}, first_waves and repeat_waves at and below the
- * residency limit, and every wide_layout value of the class, keeping a
+ * residency limit, every wide_layout value of the class, and claim_share in
+ * {0, 4, 8, 12, 16}, keeping a
  * value when the median of three timed calls improves by more than 1%
  * (less is within run-to-run noise).  Every candidate's records are
  * compared with the starting configuration's, bit for bit: a difference

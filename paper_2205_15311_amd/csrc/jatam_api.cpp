@@ -200,7 +200,7 @@ static int launch_pipeline(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit,
         const jatam_tuning_t& t = b->tune[k];
         const int fw = t.first_waves < b->occ[k][ti][0] ? t.first_waves : b->occ[k][ti][0];
         const int rw = t.repeat_waves < b->occ[k][ti][1] ? t.repeat_waves : b->occ[k][ti][1];
-        launch[k] = jatam::StageLaunch{t.refill, fw * b->cus, rw * b->cus};
+        launch[k] = jatam::StageLaunch{t.refill, fw * b->cus, rw * b->cus, t.claim_share};
     }
     return jatam::launch_batched(a, classes, launch, tm, stream, marks, launched);
 }
@@ -242,7 +242,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->graph_exec = nullptr;
     b->graph_stream = nullptr;
     for (int k = 0; k < 2; ++k)
-        b->tune[k] = jatam_tuning_t{24, 64, 64, 0};
+        b->tune[k] = jatam_tuning_t{24, 64, 64, 0, 8};
     hipDeviceProp_t prop;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -271,7 +271,8 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
         return JATAM_E_UNSUPPORTED;
     }
     const size_t n = (size_t)max_n;
-    const size_t staging = n + 64 * ((size_t)max_blocks + 1);
+    // per wave: its share of the chunks, and room for one more claim
+    const size_t staging = n + 64 * ((size_t)max_blocks * (1 + jatam::kClaimChunks) + 1);
     jatam::DeviceWorkspace& ws = b->ws;
     bool ok = batch_alloc(b, jatam::kCntWords * sizeof(uint32_t), (void**)&ws.counters) &&
               batch_alloc(b, 2 * sizeof(uint32_t), (void**)&ws.small_hash) &&
@@ -349,6 +350,7 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.narrow_max = 16;
     a.n_dev = nullptr;
     a.refill = 24;
+    a.dyn16 = 0;
     a.seg_cap = 0;
     a.small0 = b->small_hash[0];
     a.small1 = b->small_hash[1];
@@ -518,7 +520,8 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
     if (batch == nullptr || tuning == nullptr || grid_limit < 8 || grid_limit > 32 ||
         tuning->refill < 1 || tuning->refill > 64 || tuning->first_waves < 1 ||
         tuning->repeat_waves < 1 || tuning->wide_layout < 0 ||
-        tuning->wide_layout > (grid_limit > 16 ? 2 : 1))
+        tuning->wide_layout > (grid_limit > 16 ? 2 : 1) || tuning->claim_share < 0 ||
+        tuning->claim_share > 16)
         return JATAM_E_INVALID_ARG;
     batch->tune[grid_limit <= 16 ? 0 : 1] = *tuning;
     return JATAM_OK;
@@ -582,10 +585,12 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
         goto done;
     batch->tune_log.push_back({cur, cur_ms});
     // one field at a time, keeping the best value of each
-    for (int field = 0; field < 4 && rc == JATAM_OK; ++field) {
+    for (int field = 0; field < 5 && rc == JATAM_OK; ++field) {
         std::vector<int> choices;
         if (field == 0)
             choices = {8, 16, 24, 32, 48};
+        else if (field == 4)
+            choices = {0, 4, 8, 12, 16};
         else if (field == 1)
             choices = wave_choices(batch->occ[k][ti][0]);
         else if (field == 2)
@@ -597,7 +602,8 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
         for (int v : choices) {
             jatam_tuning_t trial = cur;
             int* slot = field == 0 ? &trial.refill : field == 1 ? &trial.first_waves
-                      : field == 2 ? &trial.repeat_waves : &trial.wide_layout;
+                      : field == 2 ? &trial.repeat_waves : field == 3 ? &trial.wide_layout
+                      : &trial.claim_share;
             if (*slot == v || (field == 1 && v >= batch->occ[k][ti][0] && cur.first_waves >= v) ||
                 (field == 2 && v >= batch->occ[k][ti][1] && cur.repeat_waves >= v))
                 continue;

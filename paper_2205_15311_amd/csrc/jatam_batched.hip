@@ -242,7 +242,18 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     const uint32_t wave = blockIdx.x, nwaves = gridDim.x;
     const uint32_t n_items = a.n_dev != nullptr ? *a.n_dev : (uint32_t)a.n;
     const uint32_t nchunks = (n_items + 63) / 64;
-    uint32_t next_chunk = wave;               // this wave owns chunks wave + k*nwaves
+    // Chunks below static_end are dealt out: this wave owns wave + k*nwaves.
+    // The rest are claimed kClaimChunks at a time from a device counter by
+    // the waves that run out of work first, which evens out the waves' end
+    // times.  A claim is made only while the wave's candidate segment can
+    // hold every item it has in flight plus the claim (a wave that cannot
+    // claim with nothing in flight has staged more than its dealt share of
+    // slots, so not all waves can be in that state while chunks are left).
+    const uint32_t static_end = nchunks - (uint32_t)((uint64_t)nchunks * (uint32_t)a.dyn16 / 16u);
+    uint32_t next_chunk = wave;
+    uint32_t claim_next = 0, claim_end = 0;   // chunks claimed, not yet screened
+    bool claims_left = static_end < nchunks;
+    uint32_t* const claim_ctr = a.ws.counters + kCntClaim + klass;
     uint32_t head = 0, queued = 0;            // survivor ring (wave-uniform)
     uint32_t staged = 0;                      // candidates in this wave's segment
     uint32_t* seg_idx = a.ws.cand_idx[klass] + (size_t)wave * a.seg_cap;
@@ -250,6 +261,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     WaveTally tally{{0, 0, 0, 0}};
 
     bool busy = false;
+    bool starved = false;                     // the last refill found no chunk left
     uint32_t idx = 0;
     Geno gd{0, 0, 0, 0, false};
     ModelSource<TM> m;
@@ -260,9 +272,35 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
         const uint64_t idle = __ballot(!busy);
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (nidle >= (uint32_t)a.refill || nidle == 64) {
-            while (queued < nidle && next_chunk < nchunks) {
+            starved = false;
+            while (queued < nidle) {
+                uint32_t chunk;
+                if (next_chunk < static_end) {
+                    chunk = next_chunk;
+                    next_chunk += nwaves;
+                } else {
+                    if (claim_next == claim_end) {
+                        if (!claims_left ||
+                            staged + (64u - nidle) + queued + kClaimChunks * 64u > a.seg_cap) {
+                            starved = true;
+                            break;
+                        }
+                        uint32_t base = 0;
+                        if (lane_id() == 0)
+                            base = atomicAdd(claim_ctr, (uint32_t)kClaimChunks);
+                        base = static_end + (uint32_t)__shfl((int)base, 0);
+                        if (base >= nchunks) {
+                            claims_left = false;
+                            starved = true;
+                            break;
+                        }
+                        claim_next = base;
+                        claim_end = min(base + (uint32_t)kClaimChunks, nchunks);
+                    }
+                    chunk = claim_next++;
+                }
                 // screen one chunk of the input (§3.2: what the seed decides)
-                const uint32_t pos = next_chunk * 64 + (uint32_t)lane_id();
+                const uint32_t pos = chunk * 64 + (uint32_t)lane_id();
                 uint32_t i = pos;
                 bool in_range = pos < n_items;
                 if (in_range && a.order != nullptr) {
@@ -313,7 +351,6 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                     ring_opt[slot] = opts;
                 }
                 queued += (uint32_t)__popcll(km);
-                next_chunk += nwaves;
             }
             wave_lds_sync();   // ring writes visible to the whole wave
             const uint32_t take = queued < nidle ? queued : nidle;
@@ -333,7 +370,9 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
             wave_lds_sync();   // ring slots read before they are refilled
         }
         if (__ballot(busy) == 0) {
-            if (queued == 0 && next_chunk >= nchunks)
+            // with every lane idle the refill took the whole ring, so the
+            // ring is empty exactly when no chunk was left to screen
+            if (queued == 0 && starved)
                 break;
             continue;
         }
@@ -900,6 +939,13 @@ int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
+// Zeroes one counter word (a kernel rather than a memset: graph-safe).
+__global__ void clear_word_kernel(uint32_t* w)
+{
+    if (threadIdx.x == 0)
+        *w = 0u;
+}
+
 // The first-run kernel compiled for the call's input mode.
 template <int W, int TM>
 static void launch_first(const BatchArgs& a, uint32_t nb, hipStream_t stream, int klass)
@@ -936,7 +982,9 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         const uint32_t rb = (uint32_t)launch[k].repeat_blocks;
         a.refill = launch[k].refill;
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
-        a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64);
+        a.dyn16 = launch[k].dyn16;
+        a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64) +
+                    (a.dyn16 > 0 ? (uint32_t)kClaimChunks * 64u : 0u);
         begin(kStageFirst + kStagesPerClass * k);
         if (k == 1 && a.narrow_max > 16) {
             // the 32 x 32 class reruns only the items that left the window
@@ -949,6 +997,9 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             a.n_dev = a.ws.counters + kCntOverflow;
             a.narrow_max = 16;
         }
+        if (a.dyn16 > 0)
+            hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream,
+                               a.ws.counters + kCntClaim + k);
         if (k == 0)
             launch_first<16, TM>(a, nb, stream, 0);
         else

@@ -33,9 +33,11 @@ enum {
     kCntSlice = 3,    // slice counter of a graph-replayed enumeration
     kCntCandAll = 4,  // [2] candidates before the forced-shape proof
     kCntOverflow = 6, // items that left the 16 x 16 window (rerun in 32 x 32 grids)
+    kCntClaim = 7,    // [2] chunks claimed past the static share (first-run stage)
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
+constexpr int kClaimChunks = 4;     // 64-item chunks per claim past the static share
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
 constexpr int kMaxScanBlocks = 1024;
 
@@ -74,6 +76,8 @@ struct BatchArgs {
     const uint32_t* n_dev;          // nullptr, or the item count on the device
                                     // (first-run stage; at most n)
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
+    int dyn16;                      // sixteenths of the first-run chunks claimed from a
+                                    // device counter rather than dealt out (0..16)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
     uint32_t small0, small1;        // D4 hashes of the monomer and the domino (the
                                     // workspace's small_hash, copied at creation)
@@ -98,6 +102,7 @@ struct StageLaunch {
     int refill;
     int first_blocks;
     int repeat_blocks;
+    int dyn16;
 };
 
 // occ[grid class][TM == 2 ? 0 : 1][0 first runs, 1 repeat runs]: resident

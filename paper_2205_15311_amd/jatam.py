@@ -222,7 +222,8 @@ ITEM_BYTES = 24
 class Tuning(ctypes.Structure):
     """jatam_tuning_t: launch parameters of one grid class."""
     _fields_ = [("refill", ctypes.c_int), ("first_waves", ctypes.c_int),
-                ("repeat_waves", ctypes.c_int), ("wide_layout", ctypes.c_int)]
+                ("repeat_waves", ctypes.c_int), ("wide_layout", ctypes.c_int),
+                ("claim_share", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -67,6 +67,13 @@ def test_autotune_on_s28_keeps_the_golden_records(jt):
     (32, dict(refill=8, first_waves=1, repeat_waves=2)),
     (32, dict(wide_layout=1)),
     (32, dict(wide_layout=2)),
+    (16, dict(claim_share=0)),
+    (16, dict(claim_share=16)),
+    # every chunk claimed by few waves: small segments, so waves stop
+    # claiming when their segment could not hold another claim
+    (16, dict(claim_share=16, first_waves=1, refill=64)),
+    (32, dict(claim_share=16, first_waves=1)),
+    (32, dict(claim_share=12, wide_layout=2)),
 ])
 def test_explicit_tunings_keep_records(jt, grid, tuning):
     rng = np.random.default_rng(grid + len(tuning))
@@ -80,7 +87,7 @@ def test_explicit_tunings_keep_records(jt, grid, tuning):
 def test_bad_tunings_rejected(jt):
     with jt.Batch(1024) as b:
         for bad in (dict(refill=0), dict(refill=65), dict(first_waves=0), dict(repeat_waves=0),
-                    dict(wide_layout=2)):
+                    dict(wide_layout=2), dict(claim_share=-1), dict(claim_share=17)):
             with pytest.raises(jt.JatamError):
                 b.set_tuning(16, **bad)
         with pytest.raises(jt.JatamError):
