@@ -78,7 +78,7 @@ std::vector<int> wave_choices(int occ)
 
 extern "C" {
 
-int jatam_abi_version(void) { return 3; }
+int jatam_abi_version(void) { return 4; }
 
 const char* jatam_strerror(int code)
 {

@@ -29,19 +29,11 @@ struct Geometry {
     static constexpr int kLogW = W == 16 ? 4 : 5;
     static constexpr int kCells = W * W;
     static constexpr int kWords = kCells / 32;       // bitmap words
-    // 4-bit cells of rows 0..W-2.  Row W-1 is never placed and never joins
-    // the frontier (it is ring for every G <= W), so it has no nibbles of
-    // its own: PEND comes first and row W-1's words alias the first OCC
-    // words.  update_site reads them for a ring neighbour and discards the
-    // value; run_clear zeroes them only while it clears every nonzero OCC
-    // word anyway.  Dropping the row saves W/2 bytes per lane, one more
-    // resident wave per CU at W = 16.
-    static constexpr int kPendWords = (kCells - W) / 8;
-    static constexpr int kPend = 0;
-    static constexpr int kOcc = kPendWords;
-    static constexpr int kFr = kOcc + kWords;
-    static constexpr int kLaneWords = kPendWords + 2 * kWords;
-    static_assert(kPend + kCells / 8 == kOcc + W / 8, "row W-1's nibbles alias OCC");
+    static constexpr int kPendWords = kCells / 8;    // 4-bit cells
+    static constexpr int kOcc = 0;
+    static constexpr int kFr = kWords;
+    static constexpr int kPend = 2 * kWords;
+    static constexpr int kLaneWords = 2 * kWords + kPendWords;
 };
 
 // Per-lane view of the workgroup's LDS.
@@ -282,10 +274,7 @@ template <int W, int B, class Draws>
 __device__ __forceinline__ int run_clear(LaneGrid<W, B>& g, RunState& st, Draws& dc, int G)
 {
     // occupied cells keep their tiles in PEND, and a run that ended on an
-    // event leaves frontier cells (with their PEND nibbles) behind: clear all.
-    // For the last bitmap word, the PEND words of row W-1 are OCC words 0..
-    // W/8-1, which are zero or cleared here (osum lists every nonzero OCC
-    // word), and the seed is placed after both loops.
+    // event leaves frontier cells (with their PEND nibbles) behind: clear all
     for (uint32_t s = st.osum; s; s &= s - 1) {
         const int w = __builtin_ctz(s);
         g.occ(w) = 0;
