@@ -234,7 +234,8 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *                 of at least 2^20 genotypes and 1 below.  The G <= 16
  *                 class at 1 turns the window off.
  *   claim_share   first runs: sixteenths of the input's 64-item chunks that
- *                 waves claim from a device counter, four chunks at a time,
+ *                 waves claim from a device counter, up to four chunks at a
+ *                 time (fewer when each wave gets few chunks),
  *                 once their dealt-out chunks are done (0..16; default 8).
  *                 The rest are dealt out in turn (chunk k to wave k mod the
  *                 grid).  Run lengths follow the genome's digits, so dealt-

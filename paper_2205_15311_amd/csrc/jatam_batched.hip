@@ -243,13 +243,19 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     const uint32_t n_items = a.n_dev != nullptr ? *a.n_dev : (uint32_t)a.n;
     const uint32_t nchunks = (n_items + 63) / 64;
     // Chunks below static_end are dealt out: this wave owns wave + k*nwaves.
-    // The rest are claimed kClaimChunks at a time from a device counter by
+    // The rest are claimed a few at a time from a device counter by
     // the waves that run out of work first, which evens out the waves' end
     // times.  A claim is made only while the wave's candidate segment can
     // hold every item it has in flight plus the claim (a wave that cannot
     // claim with nothing in flight has staged more than its dealt share of
     // slots, so not all waves can be in that state while chunks are left).
     const uint32_t static_end = nchunks - (uint32_t)((uint64_t)nchunks * (uint32_t)a.dyn16 / 16u);
+    // claims of up to kClaimChunks chunks, fewer when each wave gets only a
+    // few chunks (a large claim would then leave most waves without any)
+    const uint32_t per_wave = nchunks / (16u * nwaves);
+    const uint32_t claim_size = per_wave < 1u ? 1u
+                              : per_wave < (uint32_t)kClaimChunks ? per_wave
+                                                                  : (uint32_t)kClaimChunks;
     uint32_t next_chunk = wave;
     uint32_t claim_next = 0, claim_end = 0;   // chunks claimed, not yet screened
     bool claims_left = static_end < nchunks;
@@ -281,13 +287,13 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 } else {
                     if (claim_next == claim_end) {
                         if (!claims_left ||
-                            staged + (64u - nidle) + queued + kClaimChunks * 64u > a.seg_cap) {
+                            staged + (64u - nidle) + queued + claim_size * 64u > a.seg_cap) {
                             starved = true;
                             break;
                         }
                         uint32_t base = 0;
                         if (lane_id() == 0)
-                            base = atomicAdd(claim_ctr, (uint32_t)kClaimChunks);
+                            base = atomicAdd(claim_ctr, claim_size);
                         base = static_end + (uint32_t)__shfl((int)base, 0);
                         if (base >= nchunks) {
                             claims_left = false;
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                             break;
                         }
                         claim_next = base;
-                        claim_end = min(base + (uint32_t)kClaimChunks, nchunks);
+                        claim_end = min(base + claim_size, nchunks);
                     }
                     chunk = claim_next++;
                 }

@@ -37,7 +37,7 @@ enum {
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
-constexpr int kClaimChunks = 4;     // 64-item chunks per claim past the static share
+constexpr int kClaimChunks = 4;     // most 64-item chunks per claim past the static share
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
 constexpr int kMaxScanBlocks = 1024;
 
