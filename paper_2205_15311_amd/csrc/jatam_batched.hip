@@ -249,12 +249,15 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     // hold every item it has in flight plus the claim (a wave that cannot
     // claim with nothing in flight has staged more than its dealt share of
     // slots, so not all waves can be in that state while chunks are left).
-    const uint32_t static_end = nchunks - (uint32_t)((uint64_t)nchunks * (uint32_t)a.dyn16 / 16u);
-    // claims of up to kClaimChunks chunks, fewer when each wave gets only a
-    // few chunks (a large claim would then leave most waves without any)
+    // Claims are made only where every wave gets at least 16 chunks (with a
+    // chunk or two per wave there is nothing to even out), of up to
+    // kClaimChunks chunks, fewer while a large claim would leave most waves
+    // without one.
     const uint32_t per_wave = nchunks / (16u * nwaves);
-    const uint32_t claim_size = per_wave < 1u ? 1u
-                              : per_wave < (uint32_t)kClaimChunks ? per_wave
+    const uint32_t static_end =
+        per_wave < 1u ? nchunks
+                      : nchunks - (uint32_t)((uint64_t)nchunks * (uint32_t)a.dyn16 / 16u);
+    const uint32_t claim_size = per_wave < (uint32_t)kClaimChunks ? per_wave
                                                                   : (uint32_t)kClaimChunks;
     uint32_t next_chunk = wave;
     uint32_t claim_next = 0, claim_end = 0;   // chunks claimed, not yet screened

@@ -69,8 +69,6 @@ def test_autotune_on_s28_keeps_the_golden_records(jt):
     (32, dict(wide_layout=2)),
     (16, dict(claim_share=0)),
     (16, dict(claim_share=16)),
-    # every chunk claimed by few waves: small segments, so waves stop
-    # claiming when their segment could not hold another claim
     (16, dict(claim_share=16, first_waves=1, refill=64)),
     (32, dict(claim_share=16, first_waves=1)),
     (32, dict(claim_share=12, wide_layout=2)),
@@ -82,6 +80,23 @@ def test_explicit_tunings_keep_records(jt, grid, tuning):
         b.set_tuning(grid, **tuning)
         got = records(b.classify(torch.from_numpy(g.view(np.int64)).cuda(), 3, 8, grid, 20, 1))
     assert_same(got, ref.classify(g, 3, grid=grid, runs=20, seed=1), f"G={grid} {tuning}")
+
+
+@pytest.mark.parametrize("share", [8, 16])
+def test_claimed_chunks_keep_records(jt, share):
+    """Enough chunks per wave (one wave per CU, 2^18 genotypes) that the
+    waves claim chunks from the device counter, up to four at a time, with
+    segments sized for one claim beyond each wave's dealt-out share."""
+    rng = np.random.default_rng(60 + share)
+    g = rng.integers(0, 1 << 24, size=1 << 18, dtype=np.uint64)
+    with jt.Batch(1 << 18) as b:
+        b.set_tuning(16, claim_share=share, first_waves=1, refill=16)
+        tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+        got = records(b.classify(torch.from_numpy(g.view(np.int64)).cuda(), 2, 8, 16, 20, 1,
+                                 tally=tally))
+    want = ref.classify(g, 2, grid=16, runs=20, seed=1)
+    assert_same(got, want, f"claim_share={share}")
+    assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
 
 
 def test_bad_tunings_rejected(jt):
