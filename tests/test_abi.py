@@ -76,3 +76,21 @@ def test_shape_histogram_rejects_bad_arguments(lib, n, capacity):
     recs = ctypes.create_string_buffer(16)
     table = ctypes.create_string_buffer(16 * 64)
     assert lib.jatam_shape_histogram(recs, n, table, capacity, None, None) == -1
+
+
+def struct_fields(name):
+    text = open(os.path.join(ROOT, "include", "jatam.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    m = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    return re.findall(r"\b(\w+)\s*;", m.group(1))
+
+
+def test_tuning_struct_matches_the_header():
+    """The binding's jatam_tuning_t mirror has the header's fields, in order,
+    all int."""
+    import ctypes as ct
+    from paper_2205_15311_amd import jatam
+    assert [f for f, _ in jatam.Tuning._fields_] == struct_fields("jatam_tuning_t")
+    assert all(t is ct.c_int for _, t in jatam.Tuning._fields_)
+    assert ct.sizeof(jatam.Tuning) == 4 * len(jatam.Tuning._fields_)
