@@ -45,7 +45,11 @@
  * depend on the launch configuration, slice size or order of genotypes.
  *
  * Limits: 1 <= t <= 4, c in {2, 4, 8, 16} with 4*t*log2(c) <= 64, grid even
- * in [8, 32], 1 <= runs <= 64, n >= 0.
+ * in [8, 64], 1 <= runs <= 64, n >= 0.  Grids above 32 are valid models that
+ * this library does not run: calls return JATAM_E_UNSUPPORTED.  Each lane
+ * keeps its run's grid in LDS (2 occupancy/frontier bits and a 4-bit pending
+ * tile per cell of a W x W torus, W = 16 or 32); at W = 64 that is 3 KiB per
+ * lane, 192 KiB for a wave of 64 runs, more than the 160 KiB of LDS a CU has.
  */
 #ifndef JATAM_H
 #define JATAM_H
@@ -242,6 +246,14 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *                 grid).  Run lengths follow the genome's digits, so dealt-
  *                 out chunks leave some waves far more work than others;
  *                 claimed chunks go to the waves that finish first.
+ *   claim_chunks  first runs: the most 64-item chunks one claim takes
+ *                 (1..8; default 4): the work queue's chunk size.
+ *   repeat_mapping  repeat runs of the candidates that run 0 leaves
+ *                 undecided: 0 (default) gives each candidate R lanes of a
+ *                 wave, lane r making run r; 1 gives each candidate one
+ *                 lane that makes runs 1, 2, ... in turn and stops at the
+ *                 first witness, a lane that finishes taking the next
+ *                 candidate from the queue.
  */
 typedef struct {
     int refill;
@@ -249,7 +261,29 @@ typedef struct {
     int repeat_waves;
     int wide_layout;
     int claim_share;
+    int claim_chunks;
+    int repeat_mapping;
 } jatam_tuning_t;
+
+/*
+ * The batch classification of the problem statement (App. B.2: a tile set in,
+ * its classified phenotype out) over a mixed stream in one call.
+ *   batch   workspace from jatam_batch_create, n <= its max_n
+ *   items   device, n x jatam_item_t (each item its own t, grid and rng_id)
+ *   order   NULL (queue position p holds item p), or device uint32[n]: a
+ *           permutation giving the queue order (see
+ *           jatam_batch_classify_items_ordered)
+ *   tune    NULL: the workspace's parameters (defaults, or what
+ *           jatam_batch_autotune chose); else tune[0] (G <= 16) and
+ *           tune[1] (16 < G <= 32) for this call only, validated as by
+ *           jatam_batch_set_tuning
+ *   out, tally, stream, errors: as jatam_batch_classify_items.
+ * Records never depend on order or tune.
+ */
+int jatam_classify_batch(jatam_batch_t* batch, const jatam_item_t* items, int64_t n, int c,
+                         int runs, uint64_t seed, const uint32_t* order,
+                         const jatam_tuning_t* tune, jatam_result_t* out, uint64_t* tally,
+                         void* stream);
 
 /* The parameters used for grid_limit's class (8 <= grid_limit <= 32). */
 int jatam_batch_get_tuning(const jatam_batch_t* batch, int grid_limit, jatam_tuning_t* tuning);
@@ -261,8 +295,9 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
  * jatam_batch_classify_range, 1 <= n <= the workspace's max_n).  Starting
  * from the current parameters it tries, one field at a time, refill in
  * {8, 16, 24, 32, 48}, first_waves and repeat_waves at and below the
- * residency limit, every wide_layout value of the class, and claim_share in
- * {0, 4, 8, 12, 16}, keeping a
+ * residency limit, every wide_layout value of the class, claim_share in
+ * {0, 4, 8, 12, 16}, claim_chunks in {1, 2, 4, 8} and both repeat_mapping
+ * values, keeping a
  * value when the median of three timed calls improves by more than 1%
  * (less is within run-to-run noise).  Every candidate's records are
  * compared with the starting configuration's, bit for bit: a difference
@@ -328,15 +363,6 @@ int jatam_ga_offspring(const uint64_t* pop, const int32_t* fit, int64_t n, int t
                        const jatam_ga_params_t* p, int32_t generation, int64_t n_out,
                        uint64_t* out, void* stream);
 
-/*
- * One generation: n offspring (next_pop, distinct from pop), classified by
- * the pipelined path of `batch` (n <= its max_n; R runs on grid_limit with
- * assembly seed `seed`), and their fitness next_fit[i] = size if DET else 0.
- */
-int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit, int64_t n, int t,
-                  int c, int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
-                  int32_t generation, uint64_t* next_pop, int32_t* next_fit, void* stream);
-
 /* ------------------------------------------------------------------------
  * Surrogate MLP (not from the paper, which has no learned part).  Predicts a
  * genotype's class and log(1 + size) from its edge colours so work can be
@@ -373,7 +399,9 @@ int jatam_mlp_set_params(jatam_mlp_t* mlp, const float* params, void* stream);
 int jatam_mlp_get_params(jatam_mlp_t* mlp, float* params, float* grads, void* stream);
 
 /* out4[i] = network output for genome i (device, n x 4 fp32).  t: per-genome
- * tile counts (device uint8, 1..3) or NULL for t_all. */
+ * tile counts (device uint8) or NULL for t_all (1..3; JATAM_E_INVALID_ARG
+ * otherwise).  A genome whose own t is outside 1..3 is read as having no
+ * tiles (an all-zero input): the network sees at most 12 edges. */
 int jatam_mlp_forward(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
                       int64_t n, float* out4, void* stream);
 
@@ -417,6 +445,30 @@ int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* ml
                            int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
                            int32_t generation, int oversample, uint64_t* next_pop,
                            int32_t* next_fit, void* stream);
+
+/* What screens a generation: the network, the candidate workspace (at least
+ * oversample * n candidates) and the oversampling factor (>= 1). */
+typedef struct {
+    jatam_mlp_t* mlp;
+    jatam_ga_t*  ga;
+    int32_t      oversample;
+    int32_t      pad;
+} jatam_screen_t;
+
+/*
+ * One generation of the GA (§2.2, §3.1): n offspring (next_pop, distinct
+ * from pop), classified by the pipelined path of `batch` (n <= its max_n; R
+ * runs on grid_limit with assembly seed `seed`), and their fitness
+ * next_fit[i] = size if DET else 0.
+ *   surrogate  NULL: the plain GA (offspring i drawn as jatam_ga_offspring
+ *              draws it); else the screened generation of
+ *              jatam_ga_step_screened with surrogate->mlp, ->ga and
+ *              ->oversample (t <= 3).  Fitness always comes from assembly.
+ */
+int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit, int64_t n, int t,
+                  int c, int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
+                  int32_t generation, const jatam_screen_t* surrogate, uint64_t* next_pop,
+                  int32_t* next_fit, void* stream);
 
 /* ------------------------------------------------------------------------
  * Shape histogram (§3.4: the paper histograms the shape hashes of every

@@ -13,7 +13,7 @@ struct jatam_batch {
     int device;
     int64_t max_n;
     int cus;                       // compute units of the device
-    int occ[2][2][2];              // resident blocks per CU [class][tile bound][stage]
+    int occ[2][2][3];              // resident blocks per CU [class][tile bound][stage]
     jatam_tuning_t tune[2];        // launch parameters per grid class
     uint32_t small_hash[2];        // host copy of the workspace's small_hash
     std::vector<std::pair<jatam_tuning_t, double>> tune_log;   // last autotune
@@ -64,6 +64,16 @@ int make_params(int t, int c, int grid, int runs, uint64_t seed, jatam::Params* 
     return JATAM_OK;
 }
 
+// Launch parameters of the class of grid_limit within their limits.
+bool tuning_valid(int grid_limit, const jatam_tuning_t* t)
+{
+    return t->refill >= 1 && t->refill <= 64 && t->first_waves >= 1 && t->repeat_waves >= 1 &&
+           t->wide_layout >= 0 && t->wide_layout <= (grid_limit > 16 ? 2 : 1) &&
+           t->claim_share >= 0 && t->claim_share <= 16 && t->claim_chunks >= 1 &&
+           t->claim_chunks <= jatam::kMaxClaimChunks && t->repeat_mapping >= 0 &&
+           t->repeat_mapping <= 1;
+}
+
 // Candidate values of one tuning field, around the residency limit `occ`.
 std::vector<int> wave_choices(int occ)
 {
@@ -78,7 +88,7 @@ std::vector<int> wave_choices(int occ)
 
 extern "C" {
 
-int jatam_abi_version(void) { return 4; }
+int jatam_abi_version(void) { return 5; }
 
 const char* jatam_strerror(int code)
 {
@@ -183,24 +193,28 @@ static int next_marks(jatam_batch_t* b, hipEvent_t** marks, uint8_t** launched)
 constexpr int64_t kWindowMinItems = 1 << 20;
 
 static int launch_pipeline(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
-                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
+                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched,
+                           const jatam_tuning_t* tune = nullptr)
 {
+    const jatam_tuning_t* tn = tune != nullptr ? tune : b->tune;
     const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
     // G <= narrow_max runs in the 16 x 16 layout; with the window on (the
     // default) that is every G <= 32, and the 32 x 32 class reruns only the
     // items of G > 16 that left the window
-    const int w1 = b->tune[1].wide_layout;
+    const int w1 = tn[1].wide_layout;
     const bool window =
-        !b->tune[0].wide_layout && (w1 == 2 || (w1 == 0 && a.n >= kWindowMinItems));
-    a.narrow_max = b->tune[0].wide_layout ? 0 : window ? 32 : 16;
+        !tn[0].wide_layout && (w1 == 2 || (w1 == 0 && a.n >= kWindowMinItems));
+    a.narrow_max = tn[0].wide_layout ? 0 : window ? 32 : 16;
     const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
                              grid_limit == 0 || grid_limit > (window ? 16 : a.narrow_max)};
     jatam::StageLaunch launch[2];
     for (int k = 0; k < 2; ++k) {
-        const jatam_tuning_t& t = b->tune[k];
+        const jatam_tuning_t& t = tn[k];
+        const int rocc = b->occ[k][ti][t.repeat_mapping == 1 ? 2 : 1];
         const int fw = t.first_waves < b->occ[k][ti][0] ? t.first_waves : b->occ[k][ti][0];
-        const int rw = t.repeat_waves < b->occ[k][ti][1] ? t.repeat_waves : b->occ[k][ti][1];
-        launch[k] = jatam::StageLaunch{t.refill, fw * b->cus, rw * b->cus, t.claim_share};
+        const int rw = t.repeat_waves < rocc ? t.repeat_waves : rocc;
+        launch[k] = jatam::StageLaunch{t.refill,       fw * b->cus,     rw * b->cus,
+                                       t.claim_share, t.claim_chunks, t.repeat_mapping};
     }
     return jatam::launch_batched(a, classes, launch, tm, stream, marks, launched);
 }
@@ -242,7 +256,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->graph_exec = nullptr;
     b->graph_stream = nullptr;
     for (int k = 0; k < 2; ++k)
-        b->tune[k] = jatam_tuning_t{24, 64, 64, 0, 8};
+        b->tune[k] = jatam_tuning_t{24, 64, 64, 0, 8, 4, 0};
     hipDeviceProp_t prop;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -272,7 +286,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     }
     const size_t n = (size_t)max_n;
     // per wave: its share of the chunks, and room for one more claim
-    const size_t staging = n + 64 * ((size_t)max_blocks * (1 + jatam::kClaimChunks) + 1);
+    const size_t staging = n + 64 * ((size_t)max_blocks * (1 + jatam::kMaxClaimChunks) + 1);
     jatam::DeviceWorkspace& ws = b->ws;
     bool ok = batch_alloc(b, jatam::kCntWords * sizeof(uint32_t), (void**)&ws.counters) &&
               batch_alloc(b, 2 * sizeof(uint32_t), (void**)&ws.small_hash) &&
@@ -351,6 +365,7 @@ static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int
     a.n_dev = nullptr;
     a.refill = 24;
     a.dyn16 = 0;
+    a.claim_chunks = 1;
     a.seg_cap = 0;
     a.small0 = b->small_hash[0];
     a.small1 = b->small_hash[1];
@@ -423,6 +438,30 @@ int jatam_batch_classify_items_ordered(jatam_batch_t* batch, const jatam_item_t*
     a.items = items;
     a.order = order;
     return launch_timed(batch, a, 0, 4, (hipStream_t)stream);
+}
+
+int jatam_classify_batch(jatam_batch_t* batch, const jatam_item_t* items, int64_t n, int c,
+                         int runs, uint64_t seed, const uint32_t* order,
+                         const jatam_tuning_t* tune, jatam_result_t* out, uint64_t* tally,
+                         void* stream)
+{
+    jatam::Params p;
+    int rc = make_params(1, c, 16, runs, seed, &p);
+    if (rc != JATAM_OK)
+        return rc;
+    if ((rc = batch_check(batch, n, out)) != JATAM_OK)
+        return rc;
+    if ((n > 0 && items == nullptr) ||
+        (tune != nullptr && (!tuning_valid(16, &tune[0]) || !tuning_valid(32, &tune[1]))))
+        return JATAM_E_INVALID_ARG;
+    jatam::BatchArgs a = batch_args(batch, p, n, out, tally);
+    a.items = items;
+    a.order = order;
+    hipEvent_t* marks;
+    uint8_t* launched;
+    if ((rc = next_marks(batch, &marks, &launched)) != JATAM_OK)
+        return rc;
+    return launch_pipeline(batch, a, 0, 4, (hipStream_t)stream, marks, launched, tune);
 }
 
 int jatam_batch_enumerate(jatam_batch_t* batch, uint64_t first, int64_t slice, int64_t slices,
@@ -518,10 +557,7 @@ int jatam_batch_get_tuning(const jatam_batch_t* batch, int grid_limit, jatam_tun
 int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tuning_t* tuning)
 {
     if (batch == nullptr || tuning == nullptr || grid_limit < 8 || grid_limit > 32 ||
-        tuning->refill < 1 || tuning->refill > 64 || tuning->first_waves < 1 ||
-        tuning->repeat_waves < 1 || tuning->wide_layout < 0 ||
-        tuning->wide_layout > (grid_limit > 16 ? 2 : 1) || tuning->claim_share < 0 ||
-        tuning->claim_share > 16)
+        !tuning_valid(grid_limit, tuning))
         return JATAM_E_INVALID_ARG;
     batch->tune[grid_limit <= 16 ? 0 : 1] = *tuning;
     return JATAM_OK;
@@ -584,17 +620,25 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
     if ((rc = measure(ref, &cur_ms)) != JATAM_OK)
         goto done;
     batch->tune_log.push_back({cur, cur_ms});
-    // one field at a time, keeping the best value of each
-    for (int field = 0; field < 5 && rc == JATAM_OK; ++field) {
+    // one field at a time, keeping the best value of each: the repeat
+    // stage's mapping before its grid (whose residency limit it sets)
+    static const int order[7] = {0, 1, 6, 2, 3, 4, 5};
+    for (int fi = 0; fi < 7 && rc == JATAM_OK; ++fi) {
+        const int field = order[fi];
+        const int rocc = batch->occ[k][ti][cur.repeat_mapping == 1 ? 2 : 1];
         std::vector<int> choices;
         if (field == 0)
             choices = {8, 16, 24, 32, 48};
         else if (field == 4)
             choices = {0, 4, 8, 12, 16};
+        else if (field == 5)
+            choices = {1, 2, 4, 8};
+        else if (field == 6)
+            choices = {0, 1};
         else if (field == 1)
             choices = wave_choices(batch->occ[k][ti][0]);
         else if (field == 2)
-            choices = wave_choices(batch->occ[k][ti][1]);
+            choices = wave_choices(rocc);
         else if (k == 0)
             choices = {0, 1};
         else
@@ -603,9 +647,10 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
             jatam_tuning_t trial = cur;
             int* slot = field == 0 ? &trial.refill : field == 1 ? &trial.first_waves
                       : field == 2 ? &trial.repeat_waves : field == 3 ? &trial.wide_layout
-                      : &trial.claim_share;
+                      : field == 4 ? &trial.claim_share : field == 5 ? &trial.claim_chunks
+                      : &trial.repeat_mapping;
             if (*slot == v || (field == 1 && v >= batch->occ[k][ti][0] && cur.first_waves >= v) ||
-                (field == 2 && v >= batch->occ[k][ti][1] && cur.repeat_waves >= v))
+                (field == 2 && v >= rocc && cur.repeat_waves >= v))
                 continue;
             *slot = v;
             batch->tune[k] = trial;
@@ -737,8 +782,13 @@ int jatam_ga_offspring(const uint64_t* pop, const int32_t* fit, int64_t n, int t
 
 int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit, int64_t n, int t,
                   int c, int grid_limit, int runs, uint64_t seed, const jatam_ga_params_t* p,
-                  int32_t generation, uint64_t* next_pop, int32_t* next_fit, void* stream)
+                  int32_t generation, const jatam_screen_t* surrogate, uint64_t* next_pop,
+                  int32_t* next_fit, void* stream)
 {
+    if (surrogate != nullptr)
+        return jatam_ga_step_screened(surrogate->ga, batch, surrogate->mlp, pop, fit, n, t, c,
+                                      grid_limit, runs, seed, p, generation,
+                                      surrogate->oversample, next_pop, next_fit, stream);
     jatam::GaArgs g;
     int rc = ga_args(p, t, c, generation, &g);
     if (rc != JATAM_OK)
@@ -904,7 +954,7 @@ int jatam_mlp_forward(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* 
                       int64_t n, float* out4, void* stream)
 {
     if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || out4 == nullptr)) ||
-        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        (t == nullptr && (t_all < 1 || t_all > 3)))
         return JATAM_E_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     for (int64_t at = 0; at < n; at += mlp->max_batch) {
@@ -924,7 +974,7 @@ int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_
 {
     if (mlp == nullptr || n < 1 || n > mlp->max_batch || genomes == nullptr ||
         labels == nullptr || !(lr >= 0.f) ||
-        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        (t == nullptr && (t_all < 1 || t_all > 3)))
         return JATAM_E_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     int rc = jatam::mlp_launch_forward(mlp->a, genomes, t, t_all, (uint32_t)n, pad32(n), labels,
@@ -940,7 +990,7 @@ int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t,
                     int64_t n, float* scores, void* stream)
 {
     if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || scores == nullptr)) ||
-        (t == nullptr && (t_all < 1 || 4 * t_all * mlp->a.bits > 36)))
+        (t == nullptr && (t_all < 1 || t_all > 3)))
         return JATAM_E_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     // one fused pass, in pieces of at most 2^31 samples (no activations kept)
@@ -1049,6 +1099,7 @@ int jatam_ga_step_screened(jatam_ga_t* ga, jatam_batch_t* batch, jatam_mlp_t* ml
     if (rc != JATAM_OK)
         return rc;
     if (ga == nullptr || batch == nullptr || mlp == nullptr || n < 1 || oversample < 1 ||
+        oversample > 1024 ||
         n * oversample > ga->max_cand || n > batch->max_n || pop == nullptr || fit == nullptr ||
         next_pop == nullptr || next_fit == nullptr || next_pop == pop || t > 3 ||
         c != (1 << mlp->a.bits))

@@ -5,11 +5,14 @@
 // work is ~7x the total work.  Here the classification is split by what the
 // work actually is, into three stages per grid class (W = 16 or 32):
 //
-//   first_run<W>  persistent waves, each owning a fixed set of 64-genotype
-//                 input chunks.  A wave screens a chunk (decode, bond options
-//                 of the seed: an ambiguous seed neighbour is ND_SITE, a seed
-//                 with nothing to bond is a DET monomer; ~59% of S_{2,8}) and
-//                 keeps the survivors in an LDS ring.  Each lane runs the
+//   first_run<W>  persistent waves over 64-genotype input chunks: a share of
+//                 the chunks is dealt out (chunk k to wave k mod the grid),
+//                 the rest are claimed a few at a time from a device counter
+//                 by the waves that run out of work first.  A wave screens a
+//                 chunk (decode, bond options of the seed: an ambiguous seed
+//                 neighbour is ND_SITE, a seed with nothing to bond is a DET
+//                 monomer; ~59% of S_{2,8}) and keeps the survivors in an LDS
+//                 ring.  Each lane runs the
 //                 first run of one survivor; a lane that finishes takes the
 //                 next survivor at once, so lanes stay busy while run lengths
 //                 differ.  A first run ending in an event or without ever
@@ -21,15 +24,22 @@
 //                 so this orders the repeat work by its exact cost): per
 //                 segment histograms in LDS, one scan, scatter with LDS
 //                 cursors.
+//   prove<W>      one lane per candidate replays run 0 and checks whether its
+//                 shape is guarded (every growth order ends in it): then the
+//                 record is final; the other candidates are compacted.
 //   repeat<W>     R lanes per candidate, lane r making run r; the first
 //                 witness in run order (an event or a shape different from
 //                 run 0's) is found in LDS, and for DET genotypes the 8
-//                 orientation hashes are split across the group's lanes.
+//                 orientation hashes are split across the group's lanes.  Or
+//                 (repeat_seq) one lane per candidate making its runs in
+//                 turn and stopping at the first witness.
 //
-// No stage uses a global atomic on a shared counter (on MI355X those
-// serialise across the 8 XCDs): work is partitioned statically, queues are
-// per-wave segments.  Records are identical to the plain kernel's: each is a
-// pure function of the genotype, never of the schedule.
+// The only global atomic on a shared counter is the first-run claim counter,
+// taken a few chunks at a time by waves that have finished their dealt-out
+// share (same-address atomics serialise across the 8 XCDs, so claims are
+// rare); every other queue is a per-wave segment or a scan.  Records are
+// identical to the plain kernel's: each is a pure function of the genotype,
+// never of the schedule.
 #include "jatam_assembly.hpp"
 #include "jatam_internal.hpp"
 
@@ -251,14 +261,14 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     // slots, so not all waves can be in that state while chunks are left).
     // Claims are made only where every wave gets at least 16 chunks (with a
     // chunk or two per wave there is nothing to even out), of up to
-    // kClaimChunks chunks, fewer while a large claim would leave most waves
+    // claim_chunks chunks, fewer while a large claim would leave most waves
     // without one.
     const uint32_t per_wave = nchunks / (16u * nwaves);
     const uint32_t static_end =
         per_wave < 1u ? nchunks
                       : nchunks - (uint32_t)((uint64_t)nchunks * (uint32_t)a.dyn16 / 16u);
-    const uint32_t claim_size = per_wave < (uint32_t)kClaimChunks ? per_wave
-                                                                  : (uint32_t)kClaimChunks;
+    const uint32_t claim_size = per_wave < (uint32_t)a.claim_chunks ? per_wave
+                                                                    : (uint32_t)a.claim_chunks;
     uint32_t next_chunk = wave;
     uint32_t claim_next = 0, claim_end = 0;   // chunks claimed, not yet screened
     bool claims_left = static_end < nchunks;
@@ -569,9 +579,10 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
 
 // ---------------------------------------------------------------------------
 // prove<W>: one lane per candidate (in size order) replays its first run and
-// checks whether the shape is forced (shape_is_forced): then every run ends
-// in it and the record is final without the repeat runs -- DET, run 0's
-// size and hash, (size - 1) * R placements.  The other candidates are kept,
+// checks whether the shape is guarded (shape_is_guarded; forced shapes are
+// the case without conflicts): then every run ends in it and the record is
+// final without the repeat runs -- DET, run 0's size and hash, (size - 1) * R
+// placements.  The other candidates are kept,
 // in queue order, for the repeat runs: keep[pos] holds the candidate or
 // kNoCandidate, and chunk_cnt[c] the kept count of queue chunk c (64
 // positions; every chunk below n/64 is written).
@@ -874,6 +885,153 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
 }
 
 // ---------------------------------------------------------------------------
+// repeat_seq<W>: one lane per candidate, its runs made in turn.  Run 0 is
+// replayed and its occupancy kept beside the lane's grid (OCC0, the words it
+// touched); each later run is compared with it as soon as it ends, and the
+// first witness in run order (an event, or another occupancy) decides, so a
+// non-deterministic candidate makes only the runs up to its first witness.
+// A lane that is done takes the wave's next queue position: the wave owns
+// chunks k, k + grid, ... of 64 positions of the size-sorted queue, handed to
+// idle lanes in order once at least kSeqRefill of them wait.
+// ---------------------------------------------------------------------------
+constexpr int kSeqRefill = 8;
+
+template <int W, int TM, bool kTable>
+__global__ __launch_bounds__(64) void repeat_seq_kernel(const BatchArgs a, int klass)
+{
+    using Geo = Geometry<W>;
+    using Src = typename std::conditional<kTable, TableSource<TM>, ModelSource<TM>>::type;
+    const uint32_t small0 = a.small0, small1 = a.small1;
+    const uint64_t first = slice_first(a);
+    jatam_result_t* const out = slice_out(a);
+    __shared__ uint32_t smem[Geo::kLaneWords * 64];
+    __shared__ uint32_t occ0_mem[Geo::kWords * 64];   // lane j's word w at [w * 64 + j]
+    __shared__ uint4 cache_mem[kShapeCache];
+    LaneGrid<W, 64> g{smem + threadIdx.x};
+    uint32_t* const occ0 = occ0_mem + threadIdx.x;
+    g.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
+    RunState st{0, 0, 0, 0, 0, false};
+    WaveTally tally{{0, 0, 0, 0}};
+    DrawPair dc;
+    dc.reset();
+
+    const int R = a.runs;
+    const uint32_t count = a.ws.counters[kCntCand + klass];
+    const uint32_t* queue = a.ws.sorted[klass];
+    const uint32_t nwaves = gridDim.x;
+    uint32_t chunk = blockIdx.x, off = 0;   // the wave's next queue position (wave-uniform)
+    bool busy = false;
+    uint32_t idx = 0, osum0 = 0;
+    int run = 0, ev = kEvNone, steps_sum = 0, size0 = 0;
+    Geno gd{0, 0, 0, 0, false};
+    Src src;
+
+    for (;;) {
+        const uint64_t idle = __ballot(!busy);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        const bool left = chunk * 64u + off < count;
+        if (left && (nidle >= (uint32_t)kSeqRefill || nidle == 64)) {
+            if (!busy) {
+                // idle lane of rank k takes the k-th next position (at most
+                // one chunk ahead: off + k < 128)
+                const uint32_t o = off + (uint32_t)__popcll(idle & lanes_below());
+                const uint32_t pos = (o < 64u ? chunk : chunk + nwaves) * 64u + (o & 63u);
+                if (pos < count) {
+                    idx = queue[pos];
+                    gd = run_geno<W>(a, first, idx);
+                    src.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
+                    if constexpr (kTable) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d)
+                            src.side[d] = ((uint64_t)bond_table_word(src.m, 2 * d + 1) << 32) |
+                                          bond_table_word(src.m, 2 * d);
+                    }
+                    run = 0;
+                    steps_sum = 0;
+                    ev = run_start(src, g, st, dc, gd.grid);
+                    busy = true;
+                }
+            }
+            const uint32_t o = off + nidle;
+            chunk = o < 64u ? chunk : chunk + nwaves;
+            off = o & 63u;
+        }
+        if (__ballot(busy) == 0) {
+            if (!left)
+                break;
+            continue;
+        }
+        const uint32_t rid_lo = (uint32_t)gd.rng_id, rid_hi = (uint32_t)(gd.rng_id >> 32);
+        const bool stepping = busy && !run_over(ev, st, gd.grid);
+        prefetch_draws(dc, stepping, st, run, a.key0, a.key1, rid_lo, rid_hi);
+        if (stepping)
+            ev = run_step(src, g, st, dc, gd.grid, run, a.key0, a.key1, rid_lo, rid_hi);
+        const bool ended = busy && run_over(ev, st, gd.grid);
+        bool done = false, det = false;
+        int cls = 0;
+        jatam_result_t rec{0, 0, 0u, 0};
+        if (ended) {
+            steps_sum += st.steps;
+            if (ev == kEvCorrupt) {
+                rec = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
+                cls = JATAM_INVALID;
+                done = true;
+            } else if (run == 0 && ev != kEvNone) {
+                // (a candidate's run 0 ended cleanly in the first-run stage)
+                cls = ev == kEvUnbound ? JATAM_UNBOUND : JATAM_ND_SITE;
+                rec = jatam_result_t{cls, st.size, 0u, steps_sum};
+                done = true;
+            } else if (run == 0) {
+                // keep run 0's occupancy: only its nonzero words are ever read
+                for (uint32_t sw = st.osum; sw != 0; sw &= sw - 1) {
+                    const int w = __builtin_ctz(sw);
+                    occ0[w * 64] = g.occ(w);
+                }
+                osum0 = st.osum;
+                size0 = st.size;
+                run = 1;
+                ev = run_start(src, g, st, dc, gd.grid);
+            } else {
+                // occupancy only grows within a run, so osum is exactly the
+                // set of nonzero words
+                bool same = ev == kEvNone && st.osum == osum0 && st.size == size0;
+                for (uint32_t sw = osum0; same && sw != 0; sw &= sw - 1) {
+                    const int w = __builtin_ctz(sw);
+                    same = g.occ(w) == occ0[w * 64];
+                }
+                if (!same) {
+                    cls = ev == kEvUnbound ? JATAM_UNBOUND
+                        : ev == kEvAmbig   ? JATAM_ND_SITE
+                                           : JATAM_ND_RUNS;
+                    rec = jatam_result_t{cls, st.size, 0u, steps_sum};
+                    done = true;
+                } else if (run == R - 1) {
+                    cls = JATAM_DET;
+                    det = true;
+                    rec = jatam_result_t{JATAM_DET, size0, 0u, steps_sum};
+                    done = true;
+                } else {
+                    run += 1;
+                    ev = run_start(src, g, st, dc, gd.grid);
+                }
+            }
+        }
+        // the grid holds run R-1's shape, which is run 0's
+        if (__ballot(det) != 0)
+            rec.hash = det_hash(g, small0, small1, cache, det, size0, gd.grid);
+        if (done) {
+            out[idx] = rec;
+            busy = false;
+        }
+        tally.add(done, cls);
+    }
+    tally.flush(a.tally);
+}
+
+// ---------------------------------------------------------------------------
 // Hashes of the two shapes that have a single D4 class per size.
 // ---------------------------------------------------------------------------
 __global__ void small_hash_kernel(uint32_t* out)
@@ -900,7 +1058,7 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream)
 }
 
 template <int W, int TM>
-static void occupancy_of(int out[2])
+static void occupancy_of(int out[3])
 {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[0], first_run_kernel<W, TM, kInRange>,
                                                      64, 0) !=
@@ -911,9 +1069,13 @@ static void occupancy_of(int out[2])
             hipSuccess ||
         out[1] < 1)
         out[1] = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[2], repeat_seq_kernel<W, TM, true>, 64,
+                                                     0) != hipSuccess ||
+        out[2] < 1)
+        out[2] = 1;
 }
 
-void batch_occupancy(int occ[2][2][2])
+void batch_occupancy(int occ[2][2][3])
 {
     occupancy_of<16, 2>(occ[0][0]);
     occupancy_of<16, 4>(occ[0][1]);
@@ -992,8 +1154,9 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         a.refill = launch[k].refill;
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
         a.dyn16 = launch[k].dyn16;
+        a.claim_chunks = launch[k].claim_chunks;
         a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64) +
-                    (a.dyn16 > 0 ? (uint32_t)kClaimChunks * 64u : 0u);
+                    (a.dyn16 > 0 ? (uint32_t)a.claim_chunks * 64u : 0u);
         begin(kStageFirst + kStagesPerClass * k);
         if (k == 1 && a.narrow_max > 16) {
             // the 32 x 32 class reruns only the items that left the window
@@ -1036,7 +1199,20 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         begin(kStageRepeat + kStagesPerClass * k);
         // the bond table holds colours 0..7
         const bool table = a.c <= 8;
-        if (k == 0 && table)
+        if (launch[k].repeat_mapping == 1) {
+            if (k == 0 && table)
+                hipLaunchKernelGGL((repeat_seq_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream,
+                                   a, 0);
+            else if (k == 0)
+                hipLaunchKernelGGL((repeat_seq_kernel<16, TM, false>), dim3(rb), dim3(64), 0,
+                                   stream, a, 0);
+            else if (table)
+                hipLaunchKernelGGL((repeat_seq_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream,
+                                   a, 1);
+            else
+                hipLaunchKernelGGL((repeat_seq_kernel<32, TM, false>), dim3(rb), dim3(64), 0,
+                                   stream, a, 1);
+        } else if (k == 0 && table)
             hipLaunchKernelGGL((repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a, 0);
         else if (k == 0)
             hipLaunchKernelGGL((repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a, 0);

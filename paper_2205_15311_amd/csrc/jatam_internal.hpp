@@ -37,7 +37,7 @@ enum {
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
-constexpr int kClaimChunks = 4;     // most 64-item chunks per claim past the static share
+constexpr int kMaxClaimChunks = 8;  // most 64-item chunks one first-run claim may take
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
 constexpr int kMaxScanBlocks = 1024;
 
@@ -50,7 +50,9 @@ struct DeviceWorkspace {
     uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
     uint32_t* chunk_cnt[2];   // [max_n / 64 + 1] kept candidates per queue chunk
     uint32_t* chunk_sums[2];  // [max_n / 64 / kScanBlock + 1] block totals of their scan
-    uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks + 1)] per-wave segments
+    uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks * (1 + kMaxClaimChunks) + 1)]:
+                              // per-wave segments of the first-run grid, each its
+                              // dealt-out share plus one claim of slack
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
     uint32_t* overflow;       // [max_n] items to rerun in 32 x 32 grids
@@ -78,6 +80,7 @@ struct BatchArgs {
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
     int dyn16;                      // sixteenths of the first-run chunks claimed from a
                                     // device counter rather than dealt out (0..16)
+    int claim_chunks;               // most chunks one claim takes (1..kMaxClaimChunks)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
     uint32_t small0, small1;        // D4 hashes of the monomer and the domino (the
                                     // workspace's small_hash, copied at creation)
@@ -103,11 +106,14 @@ struct StageLaunch {
     int first_blocks;
     int repeat_blocks;
     int dyn16;
+    int claim_chunks;
+    int repeat_mapping;   // 0: R lanes per candidate; 1: one lane per candidate (W = 16)
 };
 
-// occ[grid class][TM == 2 ? 0 : 1][0 first runs, 1 repeat runs]: resident
-// one-wave blocks per CU of the stage kernels.
-void batch_occupancy(int occ[2][2][2]);
+// occ[grid class][TM == 2 ? 0 : 1][0 first runs, 1 repeat runs (R lanes per
+// candidate), 2 repeat runs (one lane per candidate)]: resident one-wave
+// blocks per CU of the stage kernels.
+void batch_occupancy(int occ[2][2][3]);
 int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
 // When `marks` is not null, an event is recorded on the stream before stage
 // s (marks[2s]) and after it (marks[2s+1]), and launched[s] is set.

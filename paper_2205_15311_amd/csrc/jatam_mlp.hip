@@ -58,6 +58,10 @@ __device__ __forceinline__ void refresh_bf16(const MlpArgs& a, int i, float w)
     }
 }
 
+// Tiles the network reads of a genome of t tiles: the input has 12 edge slots
+// (3 tiles), so a t outside 1..3 is read as no tiles at all (zero input).
+__device__ __forceinline__ int mlp_tiles(int t) { return t >= 1 && t <= 3 ? t : 0; }
+
 // ---------------------------------------------------------------------------
 // Layer 1: h1 = bf16(relu(sum of W1 rows + b1)); also the one-hot x (bf16).
 // ---------------------------------------------------------------------------
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(256) void mlp_layer1_kernel(MlpArgs a, const uint64
         return;
     }
     const uint64_t g = genomes[b];
-    const int t = tvec != nullptr ? tvec[b] : t_all;
+    const int t = mlp_tiles(tvec != nullptr ? tvec[b] : t_all);
     const uint32_t cmask = (uint32_t)a.c - 1u;
     float acc = 0.f;
     for (int e = 0; e < kMlpEdges; ++e) {
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void mlp_score_kernel(MlpArgs a, const uint64_
             uint32_t packed[4] = {0u, 0u, 0u, 0u};
             if (sidx < n) {
                 const uint64_t g = genomes[sidx];
-                const int t = tvec != nullptr ? tvec[sidx] : t_all;
+                const int t = mlp_tiles(tvec != nullptr ? tvec[sidx] : t_all);
                 float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 for (int e = 0; e < 4 * t; ++e) {
                     const uint32_t colour =

@@ -63,7 +63,7 @@ def lib() -> ctypes.CDLL:
         L.jatam_ga_offspring.argtypes = [vp, vp, i64, i32, i32, vp, ctypes.c_int32, i64, vp, vp]
         L.jatam_ga_offspring.restype = i32
         L.jatam_ga_step.argtypes = [vp, vp, vp, i64, i32, i32, i32, i32, u64, vp,
-                                    ctypes.c_int32, vp, vp, vp]
+                                    ctypes.c_int32, vp, vp, vp, vp]
         L.jatam_ga_step.restype = i32
         L.jatam_mlp_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
         L.jatam_mlp_create.restype = i32
@@ -114,6 +114,8 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_autotune_log.restype = i32
         L.jatam_batch_enumerate.argtypes = [vp, u64, i64, i64, i32, i32, i32, i32, u64, vp, vp,
                                             vp, i64, vp]
+        L.jatam_classify_batch.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp, vp, vp]
+        L.jatam_classify_batch.restype = i32
         L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
         L.jatam_shape_histogram.restype = i32
@@ -223,7 +225,8 @@ class Tuning(ctypes.Structure):
     """jatam_tuning_t: launch parameters of one grid class."""
     _fields_ = [("refill", ctypes.c_int), ("first_waves", ctypes.c_int),
                 ("repeat_waves", ctypes.c_int), ("wide_layout", ctypes.c_int),
-                ("claim_share", ctypes.c_int)]
+                ("claim_share", ctypes.c_int), ("claim_chunks", ctypes.c_int),
+                ("repeat_mapping", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -376,6 +379,40 @@ class Batch:
         _check(rc, "jatam_batch_classify_items")
         return rec
 
+    def classify_batch(self, items: torch.Tensor, c: int = 8, runs: int = 20, seed: int = 1,
+                       order: torch.Tensor | None = None, tune: dict | None = None,
+                       out: torch.Tensor | None = None, tally: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+        """jatam_classify_batch: items (device uint8 (n, 24)) in the queue order
+        `order` (None: as given), with launch parameters `tune` ({16: {...},
+        32: {...}} overriding fields of the workspace's for this call; None:
+        the workspace's own)."""
+        if items.dtype != torch.uint8 or items.dim() != 2 or items.shape[1] != ITEM_BYTES:
+            raise ValueError("items must be a uint8 tensor of shape (n, 24)")
+        if not items.is_cuda or not items.is_contiguous():
+            raise ValueError("items must be a contiguous device tensor")
+        n = items.shape[0]
+        rec = _records(n, items.device, out)
+        if order is not None and (order.dtype not in (torch.int32, torch.uint32)
+                                  or tuple(order.shape) != (n,) or not order.is_cuda
+                                  or not order.is_contiguous()):
+            raise ValueError("order must be a contiguous device int32 tensor of shape (n,)")
+        tp = None
+        if tune is not None:
+            pair = (Tuning * 2)()
+            for k, g in enumerate((16, 32)):
+                _check(lib().jatam_batch_get_tuning(self._h, g, ctypes.byref(pair[k])),
+                       "jatam_batch_get_tuning")
+                for f, v in tune.get(g, {}).items():
+                    setattr(pair[k], f, int(v))
+            tp = pair
+        rc = lib().jatam_classify_batch(self._h, items.data_ptr(), n, c, runs, seed,
+                                        order.data_ptr() if order is not None else None, tp,
+                                        rec.data_ptr(), self._tally_ptr(tally),
+                                        _stream_handle(stream))
+        _check(rc, "jatam_classify_batch")
+        return rec
+
     def enumerate(self, first: int, slice_n: int, slices: int, t: int, c: int = 8,
                   grid_limit: int = 16, runs: int = 20, seed: int = 1,
                   out: torch.Tensor | None = None, tally: torch.Tensor | None = None,
@@ -434,15 +471,19 @@ class Batch:
     def ga_step(self, pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
                 generation: int, c: int = 8, grid_limit: int = 32, runs: int = 20,
                 seed: int = 1, next_pop: torch.Tensor | None = None,
-                next_fit: torch.Tensor | None = None, stream=None):
-        """jatam_ga_step: (next_pop, next_fit) of one generation."""
+                next_fit: torch.Tensor | None = None, surrogate: "Screen | None" = None,
+                stream=None):
+        """jatam_ga_step: (next_pop, next_fit) of one generation; with a
+        Screen, the surrogate-screened generation."""
         _check_pop(pop, fit)
         if next_pop is None:
             next_pop = torch.empty_like(pop)
         if next_fit is None:
             next_fit = torch.empty_like(fit)
+        scr = surrogate.struct() if surrogate is not None else None
         rc = lib().jatam_ga_step(self._h, pop.data_ptr(), fit.data_ptr(), pop.shape[0], t, c,
                                  grid_limit, runs, seed, ctypes.byref(params), generation,
+                                 ctypes.byref(scr) if scr is not None else None,
                                  next_pop.data_ptr(), next_fit.data_ptr(), _stream_handle(stream))
         _check(rc, "jatam_ga_step")
         return next_pop, next_fit
@@ -599,3 +640,20 @@ class GA:
                                           _stream_handle(stream))
         _check(rc, "jatam_ga_step_screened")
         return next_pop, next_fit
+
+
+class ScreenStruct(ctypes.Structure):
+    """jatam_screen_t."""
+    _fields_ = [("mlp", ctypes.c_void_p), ("ga", ctypes.c_void_p),
+                ("oversample", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class Screen:
+    """What screens a GA generation (jatam_screen_t): a surrogate network, a
+    candidate workspace and the oversampling factor."""
+
+    def __init__(self, mlp: MLP, ga: GA, oversample: int = 4):
+        self.mlp, self.ga, self.oversample = mlp, ga, int(oversample)
+
+    def struct(self) -> ScreenStruct:
+        return ScreenStruct(self.mlp._h.value, self.ga._h.value, self.oversample, 0)

@@ -94,3 +94,32 @@ def test_tuning_struct_matches_the_header():
     assert [f for f, _ in jatam.Tuning._fields_] == struct_fields("jatam_tuning_t")
     assert all(t is ct.c_int for _, t in jatam.Tuning._fields_)
     assert ct.sizeof(jatam.Tuning) == 4 * len(jatam.Tuning._fields_)
+
+
+def test_classify_batch_rejects_bad_arguments(lib):
+    """jatam_classify_batch validates before touching the workspace."""
+    out = ctypes.create_string_buffer(16)
+    item = ctypes.create_string_buffer(24)
+    # no workspace, bad colour count, bad run count
+    assert lib.jatam_classify_batch(None, item, 1, 8, 20, 1, None, None, out, None, None) == -1
+    assert lib.jatam_classify_batch(None, item, 1, 3, 20, 1, None, None, out, None, None) == -1
+    assert lib.jatam_classify_batch(None, item, 1, 8, 0, 1, None, None, out, None, None) == -1
+
+
+def test_ga_step_rejects_missing_workspaces(lib):
+    from paper_2205_15311_amd import jatam
+    p = jatam.GAParams()
+    buf = ctypes.create_string_buffer(64)
+    scr = jatam.ScreenStruct(None, None, 4, 0)
+    # plain and screened generations without a batch workspace
+    assert lib.jatam_ga_step(None, buf, buf, 4, 3, 8, 32, 20, 1, ctypes.byref(p), 0, None,
+                             buf, buf, None) == -1
+    assert lib.jatam_ga_step(None, buf, buf, 4, 3, 8, 32, 20, 1, ctypes.byref(p), 0,
+                             ctypes.byref(scr), buf, buf, None) == -1
+
+
+def test_screen_struct_matches_the_header():
+    import ctypes as ct
+    from paper_2205_15311_amd import jatam
+    assert [f for f, _ in jatam.ScreenStruct._fields_] == struct_fields("jatam_screen_t")
+    assert ct.sizeof(jatam.ScreenStruct) == 24

@@ -118,3 +118,33 @@ def test_training_reduces_loss_on_s28_labels(jt):
             losses.append(float(loss.item()))
     first, last = np.mean(losses[:10]), np.mean(losses[-10:])
     assert last < 0.5 * first, (first, last)
+
+
+def test_tile_counts_outside_the_input_are_rejected_or_zero(jt):
+    """t_all must be 1..3 at every entry point (the input has 12 edge slots,
+    whatever the colour count); a per-genome t outside 1..3 is read as no
+    tiles, so its score is the score of an all-zero input."""
+    import ctypes
+    g = np.array([0o123456701234, 0o765432107654, 5, 0], dtype=np.uint64)
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    out4 = torch.empty((4, 4), dtype=torch.float32, device="cuda")
+    scores = torch.empty(4, dtype=torch.float32, device="cuda")
+    rec = torch.zeros((4, 4), dtype=torch.int32, device="cuda")
+    L = jt.lib()
+    for c in (2, 8):
+        with jt.MLP(64, c=c) as net:
+            for t_all in (0, 4, 9):
+                assert L.jatam_mlp_forward(net._h, dg.data_ptr(), None, t_all, 4,
+                                           out4.data_ptr(), None) == -1
+                assert L.jatam_mlp_score(net._h, dg.data_ptr(), None, t_all, 4,
+                                         scores.data_ptr(), None) == -1
+                assert L.jatam_mlp_train_step(net._h, dg.data_ptr(), None, t_all,
+                                              rec.data_ptr(), 4, ctypes.c_float(0.0), None,
+                                              None) == -1
+    with jt.MLP(64) as net:
+        net.init(7)
+        odd = net.score(dg, torch.tensor([5, 4, 255, 0], dtype=torch.uint8, device="cuda"))
+        fwd = net.forward(dg, torch.tensor([5, 4, 255, 0], dtype=torch.uint8, device="cuda"))
+        torch.cuda.synchronize()
+    assert torch.all(odd == odd[3]).item()
+    assert torch.all(fwd == fwd[3]).item()

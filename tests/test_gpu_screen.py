@@ -116,3 +116,31 @@ def test_trained_surrogate_raises_offspring_fitness(jt):
         unscreened = float(cfit.mean())
     print(f"mean fitness: unscreened {unscreened:.3f}, screened {screened:.3f}")
     assert screened > 1.3 * unscreened
+
+
+def test_ga_step_with_surrogate_is_the_screened_generation(jt):
+    """jatam_ga_step with a surrogate argument makes the screened generation
+    (same population and fitness as jatam_ga_step_screened), and without one
+    the plain generation of the oracle."""
+    rng = np.random.default_rng(6)
+    n, k = 2048, 4
+    pop = rng.integers(0, 1 << 36, size=n, dtype=np.uint64)
+    fit = rng.integers(0, 20, size=n, dtype=np.int32)
+    params = jt.GAParams(seed=5)
+    dpop = torch.from_numpy(pop.view(np.int64)).cuda()
+    dfit = torch.from_numpy(fit).cuda()
+    with jt.MLP(4096) as net, jt.GA(k * n) as ga, jt.Batch(n) as b:
+        net.init(3)
+        a_pop, a_fit = ga.step_screened(b, net, dpop, dfit, 3, params, generation=2,
+                                        oversample=k, grid_limit=32)
+        a_pop, a_fit = a_pop.cpu().numpy(), a_fit.cpu().numpy()
+        s_pop, s_fit = b.ga_step(dpop, dfit, 3, params, 2, grid_limit=32,
+                                 surrogate=jt.Screen(net, ga, k))
+        p_pop, p_fit = b.ga_step(dpop, dfit, 3, params, 2, grid_limit=32)
+        torch.cuda.synchronize()
+    assert np.array_equal(s_pop.cpu().numpy(), a_pop)
+    assert np.array_equal(s_fit.cpu().numpy(), a_fit)
+    want_pop, want_fit = ref.ga_step(pop, fit, 3, generation=2, grid=32, runs=20, seed=1,
+                                     ga_seed=5)
+    assert np.array_equal(p_pop.cpu().numpy().view(np.uint64), want_pop)
+    assert np.array_equal(p_fit.cpu().numpy(), want_fit)

@@ -72,6 +72,12 @@ def test_autotune_on_s28_keeps_the_golden_records(jt):
     (16, dict(claim_share=16, first_waves=1, refill=64)),
     (32, dict(claim_share=16, first_waves=1)),
     (32, dict(claim_share=12, wide_layout=2)),
+    (16, dict(claim_chunks=1, claim_share=16)),
+    (16, dict(claim_chunks=8)),
+    (16, dict(repeat_mapping=1)),
+    (16, dict(repeat_mapping=1, repeat_waves=1, wide_layout=1)),
+    (32, dict(repeat_mapping=1)),
+    (32, dict(repeat_mapping=1, wide_layout=2)),
 ])
 def test_explicit_tunings_keep_records(jt, grid, tuning):
     rng = np.random.default_rng(grid + len(tuning))
@@ -102,7 +108,9 @@ def test_claimed_chunks_keep_records(jt, share):
 def test_bad_tunings_rejected(jt):
     with jt.Batch(1024) as b:
         for bad in (dict(refill=0), dict(refill=65), dict(first_waves=0), dict(repeat_waves=0),
-                    dict(wide_layout=2), dict(claim_share=-1), dict(claim_share=17)):
+                    dict(wide_layout=2), dict(claim_share=-1), dict(claim_share=17),
+                    dict(claim_chunks=0), dict(claim_chunks=9), dict(repeat_mapping=-1),
+                    dict(repeat_mapping=2)):
             with pytest.raises(jt.JatamError):
                 b.set_tuning(16, **bad)
         with pytest.raises(jt.JatamError):
@@ -169,3 +177,69 @@ def test_window_and_direct_wide_layout_agree(jt, t, grid):
             got = records(b.classify(dev, t, 8, grid, 20, 1, tally=tally))
             assert_same(got, want, f"t={t} G={grid} wide_layout={wide}")
             assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
+
+
+def test_sequential_repeat_mapping_keeps_the_golden_records(jt):
+    """One lane per repeat candidate (runs in turn, stopping at the first
+    witness) over the first 2^22 genotypes of S_{2,8}: the oracle's digests."""
+    with open(os.path.join(HERE, "golden", "s28_digests.json")) as f:
+        gold = json.load(f)
+    n = gold["slice"]
+    with jt.Batch(4 * n) as b:
+        b.set_tuning(16, repeat_mapping=1)
+        tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+        out = b.classify_range(0, 4 * n, 2, 8, 16, 20, 1, tally=tally)
+        torch.cuda.synchronize()
+        rec = out.cpu().numpy()
+    for s in gold["slices"][:4]:
+        blob = rec[s["first"]:s["first"] + s["n"]].tobytes()
+        assert hashlib.sha256(blob).hexdigest() == s["sha256"], s["first"]
+    want = np.sum([s["tally"] for s in gold["slices"][:4]], axis=0).tolist()
+    assert tally.cpu().tolist() == want
+
+
+def test_classify_batch_with_order_and_call_tuning(jt):
+    """jatam_classify_batch: a mixed stream with a queue order and per-call
+    launch parameters gives the oracle's records and leaves the workspace's
+    own parameters as they were."""
+    n = 1 << 14
+    g, t, grid, items = mixed_items(jt, n)
+    want = ref.classify_items(items)
+    dev = torch.from_numpy(jt.make_items(g, t, grid)).cuda()
+    order = torch.from_numpy(np.random.default_rng(9).permutation(n).astype(np.int32)).cuda()
+    tunes = [None,
+             {16: dict(repeat_mapping=1, claim_chunks=2), 32: dict(repeat_mapping=1)},
+             {16: dict(refill=8, first_waves=2), 32: dict(wide_layout=2, claim_share=16)}]
+    with jt.Batch(n) as b:
+        before = (b.get_tuning(16), b.get_tuning(32))
+        for tune in tunes:
+            for o in (None, order):
+                tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+                got = records(b.classify_batch(dev, 8, 20, 1, order=o, tune=tune, tally=tally))
+                assert_same(got, want, f"tune={tune} order={o is not None}")
+                assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
+        assert (b.get_tuning(16), b.get_tuning(32)) == before
+        with pytest.raises(jt.JatamError):
+            b.classify_batch(dev, 8, 20, 1, tune={16: dict(repeat_mapping=3)})
+
+
+def test_staging_back_pressure_keeps_records(jt):
+    """Every item a DET candidate (run 0 drew a random word and ended clean):
+    with every chunk claimed by one wave per CU, segments fill up and waves
+    stop claiming once a claim would not fit; every item is still
+    classified."""
+    rng = np.random.default_rng(70)
+    pool = rng.integers(0, 1 << 24, size=1 << 16, dtype=np.uint64)
+    rec = ref.classify(pool, 2, grid=16, runs=20, seed=1)
+    cand = pool[(rec["cls"] == ref.DET) & (rec["size"] >= 3)
+                & (rec["steps"] == (rec["size"] - 1) * 20)]
+    assert len(cand) > 1000
+    g = np.resize(cand, 1 << 18)
+    want = ref.classify(g, 2, grid=16, runs=20, seed=1)
+    with jt.Batch(1 << 18) as b:
+        b.set_tuning(16, claim_share=16, first_waves=1, refill=16, claim_chunks=1)
+        tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+        got = records(b.classify(torch.from_numpy(g.view(np.int64)).cuda(), 2, 8, 16, 20, 1,
+                                 tally=tally))
+    assert_same(got, want, "all candidates")
+    assert tally.cpu().tolist() == [0, 0, 0, len(g)]
