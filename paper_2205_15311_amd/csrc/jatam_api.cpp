@@ -44,26 +44,6 @@ int log2_exact(int c)
     }
 }
 
-int make_params(int t, int c, int grid, int runs, uint64_t seed, jatam::Params* p)
-{
-    const int bits = log2_exact(c);
-    if (t < 1 || t > 4 || bits < 0 || 4 * t * bits > 64)
-        return JATAM_E_INVALID_ARG;
-    if (grid < 8 || grid > 64 || (grid & 1) || runs < 1 || runs > 64)
-        return JATAM_E_INVALID_ARG;
-    if (grid > 32)
-        return JATAM_E_UNSUPPORTED;
-    p->t = t;
-    p->c = c;
-    p->bits = bits;
-    p->genome_bits = 4 * t * bits;
-    p->grid = grid;
-    p->runs = runs;
-    p->key0 = (uint32_t)seed;
-    p->key1 = (uint32_t)(seed >> 32);
-    return JATAM_OK;
-}
-
 // Launch parameters of the class of grid_limit within their limits.
 bool tuning_valid(int grid_limit, const jatam_tuning_t* t)
 {
@@ -106,7 +86,7 @@ int jatam_classify(const uint64_t* genotypes, int64_t n, int t, int c, int grid_
                    uint64_t seed, jatam_result_t* out, void* stream)
 {
     jatam::Params p;
-    const int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    const int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if (n < 0 || (n > 0 && (genotypes == nullptr || out == nullptr)))
@@ -118,7 +98,7 @@ int jatam_classify_range(uint64_t first, int64_t n, int t, int c, int grid_limit
                          uint64_t seed, jatam_result_t* out, void* stream)
 {
     jatam::Params p;
-    const int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    const int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if (n < 0 || (n > 0 && out == nullptr))
@@ -185,38 +165,16 @@ static int next_marks(jatam_batch_t* b, hipEvent_t** marks, uint8_t** launched)
     return JATAM_OK;
 }
 
-// Launches the pipeline.  grid_limit: the uniform G of the call, or 0 for
-// mixed items (both grid classes).  marks/launched: timing hook or nullptr.
-// Calls from this many items up take the 16 x 16 window for 16 < G <= 32 by
-// default.  On smaller calls the window's extra stages and the reruns of the
-// items that leave it (populations of large shapes) cost more than it saves.
-constexpr int64_t kWindowMinItems = 1 << 20;
+// Launches the pipeline with the workspace's parameters, or `tune` for this
+// call.  grid_limit: the uniform G of the call, or 0 for mixed items (both
+// grid classes).  marks/launched: timing hook or nullptr.
 
-static int launch_pipeline(jatam_batch_t* b, jatam::BatchArgs a, int grid_limit, int max_t,
-                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched,
+static int launch_pipeline(jatam_batch_t* b, const jatam::BatchArgs& a, int grid_limit,
+                           int max_t, hipStream_t stream, hipEvent_t* marks, uint8_t* launched,
                            const jatam_tuning_t* tune = nullptr)
 {
-    const jatam_tuning_t* tn = tune != nullptr ? tune : b->tune;
-    const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
-    // G <= narrow_max runs in the 16 x 16 layout; with the window on (the
-    // default) that is every G <= 32, and the 32 x 32 class reruns only the
-    // items of G > 16 that left the window
-    const int w1 = tn[1].wide_layout;
-    const bool window =
-        !tn[0].wide_layout && (w1 == 2 || (w1 == 0 && a.n >= kWindowMinItems));
-    a.narrow_max = tn[0].wide_layout ? 0 : window ? 32 : 16;
-    const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
-                             grid_limit == 0 || grid_limit > (window ? 16 : a.narrow_max)};
-    jatam::StageLaunch launch[2];
-    for (int k = 0; k < 2; ++k) {
-        const jatam_tuning_t& t = tn[k];
-        const int rocc = b->occ[k][ti][t.repeat_mapping == 1 ? 2 : 1];
-        const int fw = t.first_waves < b->occ[k][ti][0] ? t.first_waves : b->occ[k][ti][0];
-        const int rw = t.repeat_waves < rocc ? t.repeat_waves : rocc;
-        launch[k] = jatam::StageLaunch{t.refill,       fw * b->cus,     rw * b->cus,
-                                       t.claim_share, t.claim_chunks, t.repeat_mapping};
-    }
-    return jatam::launch_batched(a, classes, launch, tm, stream, marks, launched);
+    return jatam::launch_tuned(tune != nullptr ? tune : b->tune, b->occ, b->cus, a, grid_limit,
+                               max_t, stream, marks, launched);
 }
 
 static int launch_timed(jatam_batch_t* b, const jatam::BatchArgs& a, int grid_limit, int max_t,
@@ -256,7 +214,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->graph_exec = nullptr;
     b->graph_stream = nullptr;
     for (int k = 0; k < 2; ++k)
-        b->tune[k] = jatam_tuning_t{24, 64, 64, 0, 8, 4, 0};
+        b->tune[k] = jatam::default_tuning();
     hipDeviceProp_t prop;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -271,48 +229,23 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
         free_batch(b);
         return JATAM_E_HIP;
     }
-    // first-run grids set the number of staging segments
-    int max_blocks = 1;
-    for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < 2; ++i)
-            max_blocks = b->occ[k][i][0] * b->cus > max_blocks ? b->occ[k][i][0] * b->cus
-                                                                : max_blocks;
-    // the size scan covers kSizeBuckets * max_blocks histogram entries in at
-    // most kMaxScanBlocks blocks
-    if ((size_t)jatam::kSizeBuckets * max_blocks >
-        (size_t)jatam::kScanBlock * jatam::kMaxScanBlocks) {
-        delete b;
+    const int max_blocks = jatam::max_first_blocks(b->occ, b->cus);
+    if (!jatam::scan_fits(max_blocks)) {
+        free_batch(b);
         return JATAM_E_UNSUPPORTED;
     }
-    const size_t n = (size_t)max_n;
-    // per wave: its share of the chunks, and room for one more claim
-    const size_t staging = n + 64 * ((size_t)max_blocks * (1 + jatam::kMaxClaimChunks) + 1);
-    jatam::DeviceWorkspace& ws = b->ws;
-    bool ok = batch_alloc(b, jatam::kCntWords * sizeof(uint32_t), (void**)&ws.counters) &&
-              batch_alloc(b, 2 * sizeof(uint32_t), (void**)&ws.small_hash) &&
-              batch_alloc(b, n * sizeof(jatam_result_t), (void**)&ws.records);
-    for (int k = 0; k < 2 && ok; ++k) {
-        ok = batch_alloc(b, (size_t)max_blocks * sizeof(uint32_t), (void**)&ws.seg_count[k]) &&
-             batch_alloc(b, (size_t)jatam::kSizeBuckets * max_blocks * sizeof(uint32_t),
-                         (void**)&ws.seg_hist[k]) &&
-             batch_alloc(b, (size_t)jatam::kMaxScanBlocks * sizeof(uint32_t),
-                         (void**)&ws.scan_sums[k]) &&
-             batch_alloc(b, (n / 64 + 1) * sizeof(uint32_t), (void**)&ws.chunk_cnt[k]) &&
-             batch_alloc(b, (n / 64 / jatam::kScanBlock + 1) * sizeof(uint32_t),
-                         (void**)&ws.chunk_sums[k]) &&
-             batch_alloc(b, staging * sizeof(uint32_t), (void**)&ws.cand_idx[k]) &&
-             batch_alloc(b, staging * sizeof(uint16_t), (void**)&ws.cand_size[k]) &&
-             batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.sorted[k]);
-    }
-    ok = ok && batch_alloc(b, n * sizeof(uint32_t), (void**)&ws.overflow);
-    if (!ok) {
+    // one region, laid out by carve_workspace
+    const size_t bytes = jatam::carve_workspace(nullptr, (size_t)max_n, max_blocks, true, nullptr);
+    uint8_t* base = nullptr;
+    if (!batch_alloc(b, bytes, (void**)&base)) {
         free_batch(b);
         return JATAM_E_HIP;
     }
-    if (jatam::batch_init_small_hash(ws.small_hash, nullptr) != JATAM_OK ||
+    jatam::carve_workspace(base, (size_t)max_n, max_blocks, true, &b->ws);
+    if (jatam::batch_init_small_hash(b->ws.small_hash, nullptr) != JATAM_OK ||
         hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(b->small_hash, ws.small_hash, sizeof(b->small_hash), hipMemcpyDeviceToHost) !=
-            hipSuccess) {
+        hipMemcpy(b->small_hash, b->ws.small_hash, sizeof(b->small_hash),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
         free_batch(b);
         return JATAM_E_HIP;
     }
@@ -346,33 +279,7 @@ static int batch_check(jatam_batch_t* b, int64_t n, const void* out)
 static jatam::BatchArgs batch_args(jatam_batch_t* b, const jatam::Params& p, int64_t n,
                                    jatam_result_t* out, uint64_t* tally)
 {
-    jatam::BatchArgs a;
-    a.genomes = nullptr;
-    a.items = nullptr;
-    a.first = 0;
-    a.n = n;
-    a.t = p.t;
-    a.grid = p.grid;
-    a.c = p.c;
-    a.bits = p.bits;
-    a.runs = p.runs;
-    a.key0 = p.key0;
-    a.key1 = p.key1;
-    a.order = nullptr;
-    a.slice = nullptr;
-    a.out_per_slice = 0;
-    a.narrow_max = 16;
-    a.n_dev = nullptr;
-    a.refill = 24;
-    a.dyn16 = 0;
-    a.claim_chunks = 1;
-    a.seg_cap = 0;
-    a.small0 = b->small_hash[0];
-    a.small1 = b->small_hash[1];
-    a.out = out;
-    a.tally = reinterpret_cast<unsigned long long*>(tally);
-    a.ws = b->ws;
-    return a;
+    return jatam::batch_args_for(p, n, out, tally, b->ws, b->small_hash);
 }
 
 int jatam_batch_classify(jatam_batch_t* batch, const uint64_t* genotypes, int64_t n, int t,
@@ -380,7 +287,7 @@ int jatam_batch_classify(jatam_batch_t* batch, const uint64_t* genotypes, int64_
                          uint64_t* tally, void* stream)
 {
     jatam::Params p;
-    int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if ((rc = batch_check(batch, n, out)) != JATAM_OK)
@@ -397,7 +304,7 @@ int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, 
                                uint64_t* tally, void* stream)
 {
     jatam::Params p;
-    int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if ((rc = batch_check(batch, n, out)) != JATAM_OK)
@@ -427,7 +334,7 @@ int jatam_batch_classify_items_ordered(jatam_batch_t* batch, const jatam_item_t*
 {
     jatam::Params p;
     // t and grid are per item; validate the shared arguments with placeholders
-    int rc = make_params(1, c, 16, runs, seed, &p);
+    int rc = jatam::make_params(1, c, 16, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if ((rc = batch_check(batch, n, out)) != JATAM_OK)
@@ -446,7 +353,7 @@ int jatam_classify_batch(jatam_batch_t* batch, const jatam_item_t* items, int64_
                          void* stream)
 {
     jatam::Params p;
-    int rc = make_params(1, c, 16, runs, seed, &p);
+    int rc = jatam::make_params(1, c, 16, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if ((rc = batch_check(batch, n, out)) != JATAM_OK)
@@ -470,7 +377,7 @@ int jatam_batch_enumerate(jatam_batch_t* batch, uint64_t first, int64_t slice, i
                           int64_t shapes_capacity, void* stream)
 {
     jatam::Params p;
-    int rc = make_params(t, c, grid_limit, runs, seed, &p);
+    int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
     if (rc != JATAM_OK)
         return rc;
     if (batch == nullptr || slice < 1 || slice > batch->max_n || slices < 1 ||
@@ -1143,3 +1050,144 @@ extern "C" int jatam_shape_histogram(const jatam_result_t* recs, int64_t n,
     return jatam::launch_shape_hist(recs, (uint64_t)n, table, log2cap, overflow, cus, nullptr,
                                     (hipStream_t)stream);
 }
+
+// ---------------------------------------------------------------------------
+// Workspace layout and launch parameters, shared by the workspace calls and
+// the call without a workspace.
+// ---------------------------------------------------------------------------
+namespace jatam {
+
+jatam_tuning_t default_tuning() { return jatam_tuning_t{24, 64, 64, 0, 8, 4, 0}; }
+
+int max_first_blocks(const int occ[2][2][3], int cus)
+{
+    int m = 1;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 2; ++i)
+            m = occ[k][i][0] * cus > m ? occ[k][i][0] * cus : m;
+    return m;
+}
+
+bool scan_fits(int max_blocks)
+{
+    // the size scan covers kSizeBuckets * max_blocks histogram entries in at
+    // most kMaxScanBlocks blocks
+    return (size_t)kSizeBuckets * max_blocks <= (size_t)kScanBlock * kMaxScanBlocks;
+}
+
+size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records,
+                       DeviceWorkspace* ws)
+{
+    size_t at = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base != nullptr ? base + at : nullptr;
+        at += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const size_t n = max_n, mb = (size_t)max_blocks;
+    // per wave: its share of the chunks, and room for one more claim
+    const size_t staging = n + 64 * (mb * (1 + kMaxClaimChunks) + 1);
+    DeviceWorkspace w;
+    w.counters = (uint32_t*)take(kCntWords * sizeof(uint32_t));
+    w.small_hash = (uint32_t*)take(2 * sizeof(uint32_t));
+    w.records = records ? (jatam_result_t*)take(n * sizeof(jatam_result_t)) : nullptr;
+    for (int k = 0; k < 2; ++k) {
+        w.seg_count[k] = (uint32_t*)take(mb * sizeof(uint32_t));
+        w.seg_hist[k] = (uint32_t*)take((size_t)kSizeBuckets * mb * sizeof(uint32_t));
+        w.scan_sums[k] = (uint32_t*)take((size_t)kMaxScanBlocks * sizeof(uint32_t));
+        w.chunk_cnt[k] = (uint32_t*)take((n / 64 + 1) * sizeof(uint32_t));
+        w.chunk_sums[k] = (uint32_t*)take((n / 64 / kScanBlock + 1) * sizeof(uint32_t));
+        w.cand_idx[k] = (uint32_t*)take(staging * sizeof(uint32_t));
+        w.cand_size[k] = (uint16_t*)take(staging * sizeof(uint16_t));
+        w.sorted[k] = (uint32_t*)take(n * sizeof(uint32_t));
+    }
+    w.overflow = (uint32_t*)take(n * sizeof(uint32_t));
+    if (ws != nullptr)
+        *ws = w;
+    return at;
+}
+
+// Calls from this many items up take the 16 x 16 window for 16 < G <= 32 by
+// default.  On smaller calls the window's extra stages and the reruns of the
+// items that leave it (populations of large shapes) cost more than it saves.
+constexpr int64_t kWindowMinItems = 1 << 20;
+
+int launch_tuned(const jatam_tuning_t tn[2], const int occ[2][2][3], int cus, BatchArgs a,
+                 int grid_limit, int max_t, hipStream_t stream, hipEvent_t* marks,
+                 uint8_t* launched)
+{
+    const int tm = max_t <= 2 ? 2 : 4, ti = tm == 2 ? 0 : 1;
+    // G <= narrow_max runs in the 16 x 16 layout; with the window on (the
+    // default) that is every G <= 32, and the 32 x 32 class reruns only the
+    // items of G > 16 that left the window
+    const int w1 = tn[1].wide_layout;
+    const bool window =
+        !tn[0].wide_layout && (w1 == 2 || (w1 == 0 && a.n >= kWindowMinItems));
+    a.narrow_max = tn[0].wide_layout ? 0 : window ? 32 : 16;
+    const bool classes[2] = {grid_limit == 0 || grid_limit <= a.narrow_max,
+                             grid_limit == 0 || grid_limit > (window ? 16 : a.narrow_max)};
+    StageLaunch launch[2];
+    for (int k = 0; k < 2; ++k) {
+        const jatam_tuning_t& t = tn[k];
+        const int rocc = occ[k][ti][t.repeat_mapping == 1 ? 2 : 1];
+        const int fw = t.first_waves < occ[k][ti][0] ? t.first_waves : occ[k][ti][0];
+        const int rw = t.repeat_waves < rocc ? t.repeat_waves : rocc;
+        launch[k] = StageLaunch{t.refill,       fw * cus,       rw * cus,
+                                t.claim_share, t.claim_chunks, t.repeat_mapping};
+    }
+    return launch_batched(a, classes, launch, tm, stream, marks, launched);
+}
+
+BatchArgs batch_args_for(const Params& p, int64_t n, jatam_result_t* out, uint64_t* tally,
+                         const DeviceWorkspace& ws, const uint32_t small_hash[2])
+{
+    BatchArgs a;
+    a.genomes = nullptr;
+    a.items = nullptr;
+    a.first = 0;
+    a.n = n;
+    a.t = p.t;
+    a.grid = p.grid;
+    a.c = p.c;
+    a.bits = p.bits;
+    a.runs = p.runs;
+    a.key0 = p.key0;
+    a.key1 = p.key1;
+    a.order = nullptr;
+    a.slice = nullptr;
+    a.out_per_slice = 0;
+    a.narrow_max = 16;
+    a.n_dev = nullptr;
+    a.refill = 24;
+    a.dyn16 = 0;
+    a.claim_chunks = 1;
+    a.seg_cap = 0;
+    a.small0 = small_hash[0];
+    a.small1 = small_hash[1];
+    a.out = out;
+    a.tally = reinterpret_cast<unsigned long long*>(tally);
+    a.ws = ws;
+    return a;
+}
+
+int make_params(int t, int c, int grid, int runs, uint64_t seed, Params* p)
+{
+    const int bits = log2_exact(c);
+    if (t < 1 || t > 4 || bits < 0 || 4 * t * bits > 64)
+        return JATAM_E_INVALID_ARG;
+    if (grid < 8 || grid > 64 || (grid & 1) || runs < 1 || runs > 64)
+        return JATAM_E_INVALID_ARG;
+    if (grid > 32)
+        return JATAM_E_UNSUPPORTED;
+    p->t = t;
+    p->c = c;
+    p->bits = bits;
+    p->genome_bits = 4 * t * bits;
+    p->grid = grid;
+    p->runs = runs;
+    p->key0 = (uint32_t)seed;
+    p->key1 = (uint32_t)(seed >> 32);
+    return JATAM_OK;
+}
+
+}  // namespace jatam

@@ -114,6 +114,29 @@ struct StageLaunch {
 // candidate), 2 repeat runs (one lane per candidate)]: resident one-wave
 // blocks per CU of the stage kernels.
 void batch_occupancy(int occ[2][2][3]);
+// Default launch parameters of a grid class.
+jatam_tuning_t default_tuning();
+// Largest first-run grid (one-wave blocks) over the classes and tile bounds.
+int max_first_blocks(const int occ[2][2][3], int cus);
+// Whether the size scan can cover that many first-run blocks.
+bool scan_fits(int max_blocks);
+// Lays out a DeviceWorkspace for calls of up to max_n genotypes and first-run
+// grids of up to max_blocks blocks in one region at `base` (pieces aligned to
+// 256 bytes); `records` includes the GA generation's record array.  Returns
+// the region's size in bytes; with base == nullptr only the size.
+size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records,
+                       DeviceWorkspace* ws);
+// Validates and digests the arguments shared by every classification call.
+int make_params(int t, int c, int grid, int runs, uint64_t seed, Params* p);
+// Arguments of a pipelined call over a workspace (range mode, no order).
+BatchArgs batch_args_for(const Params& p, int64_t n, jatam_result_t* out, uint64_t* tally,
+                         const DeviceWorkspace& ws, const uint32_t small_hash[2]);
+// Launches the pipeline with launch parameters tn[grid class], capped by the
+// residency limits occ on a device of `cus` compute units.  grid_limit: the
+// call's uniform G, or 0 for mixed items (both classes).
+int launch_tuned(const jatam_tuning_t tn[2], const int occ[2][2][3], int cus, BatchArgs a,
+                 int grid_limit, int max_t, hipStream_t stream, hipEvent_t* marks,
+                 uint8_t* launched);
 int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream);
 // When `marks` is not null, an event is recorded on the stream before stage
 // s (marks[2s]) and after it (marks[2s+1]), and launched[s] is set.
