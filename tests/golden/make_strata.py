@@ -62,17 +62,17 @@ def main():
             recs = ref.classify_items(mixed_items(g[idx], t[idx], grid[idx]), 8, R, SEED)
             strata[f"t{tt}_g{G}"] = summary(recs)
             print(f"mixed t={tt} G={G}: {time.time() - t0:.0f} s", flush=True)
-    out["mixed"] = {"n": MIXED_N, "strata": strata}
+    out["mixed"] = {"total": MIXED_N, "strata": strata}
     del g, t, grid
 
     first = inputs.three_tile_slice_start(SLICE_N)
     gs = np.uint64(first) + np.arange(0, SLICE_N, SLICE_STRIDE, dtype=np.uint64)
-    out["slice"] = {"first": int(first), "n": SLICE_N, "stride": SLICE_STRIDE,
+    out["slice"] = {"first": int(first), "total": SLICE_N, "stride": SLICE_STRIDE,
                     **summary(ref.classify(gs, 3, grid=32, runs=R, seed=SEED))}
     print(f"slice: {time.time() - t0:.0f} s", flush=True)
 
     gsamp = inputs.three_tile_sample(SAMPLE_N)[::SAMPLE_STRIDE]
-    out["sample"] = {"n": SAMPLE_N, "stride": SAMPLE_STRIDE,
+    out["sample"] = {"total": SAMPLE_N, "stride": SAMPLE_STRIDE,
                      **summary(ref.classify(gsamp, 3, grid=32, runs=R, seed=SEED))}
     print(f"sample: {time.time() - t0:.0f} s", flush=True)
     with open(os.path.join(HERE, "workload_strata.json"), "w") as f:

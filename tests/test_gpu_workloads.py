@@ -1,15 +1,23 @@
 """The larger workloads at their full sizes, through the C ABI, in the launch
 configuration the library uses for them (one pipelined call per slice).
 
-Parity here is on outputs the oracle can compute one by one (sampled
-records, every record of a class of inputs small enough to enumerate) and on
-properties that hold at any size:
+Parity here is on stratified subsets of 2^22 records each, compared with the
+oracle's records of the same inputs through tests/golden/workload_strata.json
+(per-2^18-record SHA-256 digests written by tests/golden/make_strata.py,
+which calls only the oracle; a differing chunk is re-run on the oracle here
+and its differing records are printed): every (t, G) stratum of the mixed
+stream, every 256th genotype of the 2^30 slice, every 64th of the 2^28
+sample.  Also on every record of a class of inputs small enough to enumerate
+(one-tile items) and on properties that hold at any size:
   - the device tally equals the class counts of the records;
   - a non-DET record has hash 0; a DET record has size >= 1 and
     steps = (size - 1) * R, or size - 1 when run 0 drew no random word
     (its runs are then identical, §3.2);
   - equal items (genome, t, grid, rng_id) give equal records.
 Inputs: tests/inputs.py (numpy's Philox generator, seeded)."""
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -22,6 +30,27 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 R = 20
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def strata():
+    with open(os.path.join(HERE, "golden", "workload_strata.json")) as f:
+        return json.load(f)
+
+
+def check_stratum(recs, gold, oracle_chunk, label):
+    """recs: the GPU's records of a stratum; gold: its digests and tally;
+    oracle_chunk(lo, hi): the oracle's records of positions lo..hi-1, run
+    only for a chunk whose digest differs."""
+    assert len(recs) == gold["n"], label
+    ch = gold["chunk"]
+    for k, want in enumerate(gold["sha256"]):
+        part = recs[k * ch:(k + 1) * ch]
+        if hashlib.sha256(part.tobytes()).hexdigest() != want:
+            assert_same(part, oracle_chunk(k * ch, (k + 1) * ch), f"{label} chunk {k}")
+            pytest.fail(f"{label} chunk {k}: digest differs, records equal the oracle's")
+    assert [int(np.sum(recs["cls"] == k)) for k in range(4)] == gold["tally"], label
 
 
 @pytest.fixture(scope="module")
@@ -59,11 +88,11 @@ def check_properties(recs, tally, label):
     assert np.all(ok), (label, det[~ok][:4])
 
 
-def test_mixed_stream_2e26_one_call(jt):
+def test_mixed_stream_2e26_one_call(jt, strata):
     """2^26 items of 1-3 tiles on 16x16 or 32x32 grids in ONE call.  Every
     one-tile record (about a third) is checked against the oracle, since the
-    4096 x 2 distinct one-tile items are few; 2^15 sampled records of the
-    rest are too."""
+    4096 x 2 distinct one-tile items are few; the first 2^22 items of each
+    (t, G) stratum against the oracle's digests."""
     n = 1 << 26
     g, t, grid = inputs.mixed_stream(n)
     items = jt.make_items(g, t, grid)
@@ -90,24 +119,34 @@ def test_mixed_stream_2e26_one_call(jt):
         sel = one[grid[one] == G]
         assert_same(recs[sel], want[g[sel].astype(np.int64)], f"one-tile items, G={G}")
 
-    # a sample of the rest
-    rest = np.nonzero(t != 1)[0]
-    pick = np.sort(np.random.default_rng(1).choice(rest, size=1 << 15, replace=False))
-    it = np.zeros(len(pick), dtype=ref.ITEM)
-    it["genome"], it["t"], it["grid"] = g[pick], t[pick], grid[pick]
-    it["rng_id"] = g[pick] | (t[pick].astype(np.uint64) << np.uint64(56))
-    assert_same(recs[pick], ref.classify_items(it, 8, R, 1), "mixed stream sample")
+    # 2^22 items of every (t, G) stratum
+    assert strata["mixed"]["total"] == n
+    for tt in (1, 2, 3):
+        for G in (16, 32):
+            gold = strata["mixed"]["strata"][f"t{tt}_g{G}"]
+            idx = np.nonzero((t == tt) & (grid == G))[0][:gold["n"]]
+
+            def oracle_chunk(lo, hi, idx=idx):
+                sel = idx[lo:hi]
+                it = np.zeros(len(sel), dtype=ref.ITEM)
+                it["genome"], it["t"], it["grid"] = g[sel], t[sel], grid[sel]
+                it["rng_id"] = g[sel] | (t[sel].astype(np.uint64) << np.uint64(56))
+                return ref.classify_items(it, 8, R, 1)
+
+            check_stratum(recs[idx], gold, oracle_chunk, f"mixed t={tt} G={G}")
 
 
-def test_three_tile_slice_2e30_g32(jt):
+def test_three_tile_slice_2e30_g32(jt, strata):
     """A contiguous 2^30-genotype slice of the three-tile space at G=32, in
-    four pipelined calls of 2^28: the slice's first and last 4096 records and
-    2^13 sampled records per call equal the oracle's; properties on all."""
+    four pipelined calls of 2^28: the slice's first and last 4096 records
+    and every 256th record equal the oracle's; properties on all."""
     n, per = 1 << 30, 1 << 28
     first = inputs.three_tile_slice_start(n)
+    gold = strata["slice"]
+    assert gold["first"] == first and gold["total"] == n and per % gold["stride"] == 0
     out = torch.empty((per, 4), dtype=torch.int32, device="cuda")
-    rng = np.random.default_rng(3)
     total = np.zeros(4, dtype=np.int64)
+    strided = []
     t_gpu = 0.0
     with jt.Batch(per) as b:
         for k in range(n // per):
@@ -122,9 +161,7 @@ def test_three_tile_slice_2e30_g32(jt):
             tl = tally.cpu().tolist()
             check_properties(recs, tl, f"slice part {k}")
             total += tl
-            pick = np.sort(rng.choice(per, size=1 << 13, replace=False))
-            want = ref.classify(np.uint64(lo) + pick.astype(np.uint64), 3, grid=32, runs=R, seed=1)
-            assert_same(recs[pick], want, f"slice part {k} sample")
+            strided.append(recs[::gold["stride"]].copy())
             if k == 0:
                 assert_same(recs[:4096], ref.classify_range(lo, 4096, 3, grid=32, runs=R, seed=1),
                             "slice head")
@@ -133,11 +170,16 @@ def test_three_tile_slice_2e30_g32(jt):
                                                              runs=R, seed=1), "slice tail")
     print(f"three-tile slice at {first}: {n / t_gpu / 1e6:.1f} M genotypes/s, tally {total.tolist()}",
           flush=True)
+    stride = gold["stride"]
+    check_stratum(np.concatenate(strided), gold,
+                  lambda lo, hi: ref.classify(np.uint64(first) + np.arange(lo, hi, dtype=np.uint64)
+                                              * np.uint64(stride), 3, grid=32, runs=R, seed=1),
+                  "slice, every 256th")
 
 
-def test_three_tile_sample_2e28_g32(jt):
-    """2^28 uniform three-tile genotypes at G=32 in one call: 2^14 sampled
-    records equal the oracle's; properties on all."""
+def test_three_tile_sample_2e28_g32(jt, strata):
+    """2^28 uniform three-tile genotypes at G=32 in one call: every 64th
+    record equals the oracle's; properties on all."""
     n = 1 << 28
     g = inputs.three_tile_sample(n)
     dg = torch.from_numpy(g.view(np.int64)).cuda()
@@ -153,9 +195,12 @@ def test_three_tile_sample_2e28_g32(jt):
     recs = records(rec)
     del rec
     check_properties(recs, tally.cpu().tolist(), "three-tile sample")
-    pick = np.sort(np.random.default_rng(4).choice(n, size=1 << 14, replace=False))
-    assert_same(recs[pick], ref.classify(g[pick], 3, grid=32, runs=R, seed=1),
-                "three-tile sample")
+    gold = strata["sample"]
+    assert gold["total"] == n
+    gs = g[::gold["stride"]]
+    check_stratum(recs[::gold["stride"]].copy(), gold,
+                  lambda lo, hi: ref.classify(gs[lo:hi], 3, grid=32, runs=R, seed=1),
+                  "sample, every 64th")
 
 
 def test_ga_population_65536_g32_chain(jt):
