@@ -492,6 +492,23 @@ int jatam_ga_step(jatam_batch_t* batch, const uint64_t* pop, const int32_t* fit,
 int jatam_shape_histogram(const jatam_result_t* recs, int64_t n, jatam_shape_count_t* table,
                           int64_t capacity, uint64_t* overflow, void* stream);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * pipelined classification of jatam_batch_classify (same records, the
+ * default launch parameters) with its queues in a static 32 MiB device array
+ * of the library, one per GPU, held until the process ends, instead of a
+ * jatam_batch_t.  n <= 2^18 (JATAM_E_INVALID_ARG above).  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU race and must
+ * be serialised (one stream).  The first call on each device sets up (the
+ * array's address, a kernel and a copy on the null stream, synchronised), so
+ * it must not be captured; later calls only launch kernels on `stream` and
+ * call no allocating routine.  Other arguments as for jatam_batch_classify.
+ * ------------------------------------------------------------------------ */
+int jatam_classify_static(const uint64_t* genotypes, int64_t n, int t, int c, int grid_limit,
+                          int runs, uint64_t seed, jatam_result_t* out, uint64_t* tally,
+                          void* stream);
+
 /* Static description of an error code. */
 const char* jatam_strerror(int code);
 

@@ -5,6 +5,6 @@ package only binds it.
 """
 from .jatam import (CLASS_NAMES, DET, GA, INVALID, MLP, ND_RUNS, ND_SITE, UNBOUND,  # noqa: F401
                     Batch, GAParams, JatamError, Screen, Tuning, abi_version, classify,
-                    classify_range, ga_offspring,
+                    classify_range, classify_static, ga_offspring,
                     lib, make_items, records_to_numpy, shape_histogram,
                     shape_table_to_numpy, strerror)

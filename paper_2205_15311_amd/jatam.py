@@ -116,6 +116,8 @@ def lib() -> ctypes.CDLL:
                                             vp, i64, vp]
         L.jatam_classify_batch.argtypes = [vp, vp, i64, i32, i32, u64, vp, vp, vp, vp, vp]
         L.jatam_classify_batch.restype = i32
+        L.jatam_classify_static.argtypes = [vp, i64, i32, i32, i32, i32, u64, vp, vp, vp]
+        L.jatam_classify_static.restype = i32
         L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
         L.jatam_shape_histogram.restype = i32
@@ -173,6 +175,28 @@ def classify_range(first: int, n: int, t: int, c: int = 8, grid_limit: int = 16,
     rc = lib().jatam_classify_range(first, n, t, c, grid_limit, runs, seed, rec.data_ptr(),
                                     _stream_handle(stream))
     _check(rc, "jatam_classify_range")
+    return rec
+
+
+STATIC_MAX_N = 1 << 18
+
+
+def classify_static(genotypes: torch.Tensor, t: int, c: int = 8, grid_limit: int = 16,
+                    runs: int = 20, seed: int = 1, out: torch.Tensor | None = None,
+                    tally: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """jatam_classify_static: the pipelined path with the library's static
+    device array as its workspace (n <= 2^18; no device allocation by the
+    library)."""
+    if genotypes.dtype not in (torch.int64, torch.uint64) or genotypes.dim() != 1:
+        raise ValueError("genotypes must be a 1-D int64/uint64 tensor")
+    if not genotypes.is_cuda or not genotypes.is_contiguous():
+        raise ValueError("genotypes must be a contiguous device tensor")
+    n = genotypes.shape[0]
+    rec = _records(n, genotypes.device, out)
+    rc = lib().jatam_classify_static(genotypes.data_ptr(), n, t, c, grid_limit, runs, seed,
+                                     rec.data_ptr(), Batch._tally_ptr(tally),
+                                     _stream_handle(stream))
+    _check(rc, "jatam_classify_static")
     return rec
 
 
