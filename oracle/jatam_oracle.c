@@ -756,3 +756,197 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
                   NULL, NULL, NULL, NULL, 0, 0 };
     return run_job(&job, threads);
 }
+
+/* ------------------------------------------------------------------------ */
+/* True class by exhaustive exploration of every growth order.               */
+/*                                                                           */
+/* The k runs of §3.2 sample growth orders; a genotype is deterministic when */
+/* every order ends in one shape without an event, and k runs can miss an    */
+/* order that shows otherwise (the misclassification that falls with k,      */
+/* §4.1).  Here every order is followed: a state is the set of placed        */
+/* (cell, tile) pairs, states are visited breadth first, each once, and a    */
+/* state is analysed from scratch (every occupied cell's neighbours, the     */
+/* isotropic check of §3.2).  The exploration stops at the first event (a    */
+/* bondable ring site or an ambiguous site) or at a second terminal shape    */
+/* (occupancy, compared without rotation): the genotype is then not         */
+/* deterministic.  More than `cap` states: undecided.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t* arena;        /* each state: its (cell << 8 | tile) pairs, ascending */
+    int64_t arena_used, arena_cap;
+    int64_t* start;        /* state k's first pair in the arena                   */
+    int32_t* len;          /* state k's pair count                                */
+    int64_t n, cap;
+    int64_t* slot;         /* open addressing: state index + 1, 0 = empty         */
+    int64_t nslots;
+    int64_t* slot_of;      /* state k's slot, to empty the table afterwards       */
+} state_set_t;
+
+static uint64_t pairs_hash(const int32_t* p, int len)
+{
+    uint64_t h = 1469598103934665603ull;   /* FNV-1a over the pairs */
+    for (int i = 0; i < len; ++i) {
+        h ^= (uint32_t)p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+/* Adds the state unless present.  Returns 1 if added, 0 if present, -1 if
+ * the set is full. */
+static int state_add(state_set_t* s, const int32_t* p, int len)
+{
+    uint64_t h = pairs_hash(p, len) & (uint64_t)(s->nslots - 1);
+    for (;;) {
+        int64_t k = s->slot[h];
+        if (k == 0)
+            break;
+        k -= 1;
+        if (s->len[k] == len && memcmp(s->arena + s->start[k], p, sizeof(int32_t) * len) == 0)
+            return 0;
+        h = (h + 1) & (uint64_t)(s->nslots - 1);
+    }
+    if (s->n == s->cap)
+        return -1;
+    if (s->arena_used + len > s->arena_cap) {
+        int64_t nc = s->arena_cap * 2 + len;
+        int32_t* na = (int32_t*)realloc(s->arena, sizeof(int32_t) * nc);
+        if (!na)
+            return -1;
+        s->arena = na;
+        s->arena_cap = nc;
+    }
+    memcpy(s->arena + s->arena_used, p, sizeof(int32_t) * len);
+    s->start[s->n] = s->arena_used;
+    s->len[s->n] = len;
+    s->slot_of[s->n] = (int64_t)h;
+    s->arena_used += len;
+    s->slot[h] = ++s->n;
+    return 1;
+}
+
+enum { TRUTH_DET = 0, TRUTH_ND = 1, TRUTH_CAPPED = 2 };
+
+static int explore_all(const model_t* m, grid_t* g, int64_t cap, state_set_t* s,
+                       uint8_t* term, uint8_t* occ, int* size_out, uint32_t* hash_out,
+                       int64_t* states_out)
+{
+    int W = g->W, cells = W * W;
+    int32_t* cur = (int32_t*)malloc(sizeof(int32_t) * (cells + 1));
+    int32_t* nxt = (int32_t*)malloc(sizeof(int32_t) * (cells + 1));
+    int verdict = TRUTH_DET, have_term = 0, term_size = 0;
+    s->n = 0;
+    s->arena_used = 0;
+    s->cap = cap;
+    int centre = (g->G / 2) * W + g->G / 2;
+    cur[0] = (centre << 8) | m->canon[0];
+    state_add(s, cur, 1);
+    for (int64_t k = 0; k < s->n; ++k) {
+        int len = s->len[k];
+        memcpy(cur, s->arena + s->start[k], sizeof(int32_t) * len);
+        /* the state's grid, analysed from scratch */
+        for (int i = 0; i < cells; ++i) {
+            g->cell[i] = -1;
+            g->pend[i] = -1;
+        }
+        g->nf = 0;
+        for (int i = 0; i < len; ++i)
+            g->cell[cur[i] >> 8] = (int16_t)(cur[i] & 0xFF);
+        int ev = EV_NONE;
+        for (int i = 0; i < len; ++i) {
+            int e = update(m, g, cur[i] >> 8);
+            if (e != EV_NONE)
+                ev = e;
+        }
+        if (ev != EV_NONE) {
+            verdict = TRUTH_ND;
+            break;
+        }
+        if (g->nf == 0) {
+            occupancy_of(g, occ);
+            if (!have_term) {
+                memcpy(term, occ, (size_t)cells);
+                term_size = len;
+                have_term = 1;
+            } else if (memcmp(term, occ, (size_t)cells) != 0) {
+                verdict = TRUTH_ND;
+                break;
+            }
+            continue;
+        }
+        for (int j = 0; j < g->nf; ++j) {
+            int q = g->front[j];
+            /* the state plus (q, its pending tile), pairs kept ascending */
+            int o = 0, placed = 0;
+            for (int i = 0; i < len; ++i) {
+                if (!placed && (cur[i] >> 8) > q) {
+                    nxt[o++] = (q << 8) | g->pend[q];
+                    placed = 1;
+                }
+                nxt[o++] = cur[i];
+            }
+            if (!placed)
+                nxt[o++] = (q << 8) | g->pend[q];
+            if (state_add(s, nxt, o) < 0) {
+                verdict = TRUTH_CAPPED;
+                break;
+            }
+        }
+        if (verdict == TRUTH_CAPPED)
+            break;
+    }
+    *states_out = s->n;
+    for (int64_t k = 0; k < s->n; ++k)   /* empty the table for the next genotype */
+        s->slot[s->slot_of[k]] = 0;
+    *size_out = verdict == TRUTH_DET ? term_size : 0;
+    *hash_out = verdict == TRUTH_DET ? hash_of_occupancy(term, W) : 0;
+    free(cur);
+    free(nxt);
+    return verdict;
+}
+
+int jref_true_class(const uint64_t* genomes, int64_t n, int t, int c, int grid, int64_t cap,
+                    jref_result_t* out)
+{
+    if (jref_check_args(t, c, grid, 1) != JREF_OK || n < 0 || cap < 1 || cap > (1 << 24))
+        return JREF_E_INVALID_ARG;
+    state_set_t s;
+    s.nslots = 1;
+    while (s.nslots < 2 * cap)
+        s.nslots *= 2;
+    s.arena_cap = 1 << 16;
+    s.arena = (int32_t*)malloc(sizeof(int32_t) * s.arena_cap);
+    s.start = (int64_t*)malloc(sizeof(int64_t) * cap);
+    s.len = (int32_t*)malloc(sizeof(int32_t) * cap);
+    s.slot = (int64_t*)calloc((size_t)s.nslots, sizeof(int64_t));
+    s.slot_of = (int64_t*)malloc(sizeof(int64_t) * cap);
+    workspace_t* ws = (workspace_t*)malloc(sizeof(workspace_t));
+    int rc = JREF_OK;
+    if (!s.arena || !s.start || !s.len || !s.slot || !s.slot_of || !ws)
+        rc = JREF_E_INVALID_ARG;
+    for (int64_t i = 0; i < n && rc == JREF_OK; ++i) {
+        if (!genome_fits(genomes[i], t, c)) {
+            rc = JREF_E_INVALID_ARG;
+            break;
+        }
+        model_t m;
+        build_model(genomes[i], t, c, &m);
+        ws->g.G = grid;
+        ws->g.W = grid + 1;
+        int size = 0;
+        uint32_t hv = 0;
+        int64_t states = 0;
+        int v = explore_all(&m, &ws->g, cap, &s, ws->occ0, ws->occ, &size, &hv, &states);
+        out[i].cls = v == TRUTH_DET ? JREF_DET : v == TRUTH_ND ? JREF_ND_SITE : -2;
+        out[i].size = size;
+        out[i].hash = hv;
+        out[i].steps = (int32_t)states;
+    }
+    free(s.arena);
+    free(s.start);
+    free(s.len);
+    free(s.slot);
+    free(s.slot_of);
+    free(ws);
+    return rc;
+}

@@ -117,6 +117,16 @@ int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
                    int run, uint64_t seed, int32_t* cells_out, int cap,
                    int* event, int* choice);
 
+/* True class of n genotypes of t tiles on a G-grid by exhaustive
+ * exploration of every growth order, breadth first over the event-free
+ * states ((cell, tile) sets), each visited once.  out[i]: cls JREF_DET (one
+ * terminal shape and no event reachable; size and hash of that shape),
+ * JREF_ND_SITE (an event or a second terminal shape is reachable; size and
+ * hash 0), or -2 (more than cap states; undecided); steps = states visited
+ * when the exploration stopped.  Single-threaded. */
+int jref_true_class(const uint64_t* genomes, int64_t n, int t, int c, int grid, int64_t cap,
+                    jref_result_t* out);
+
 /* ---- genetic algorithm (jatam_ga_oracle.c) ---- */
 typedef struct {
     uint64_t seed;        /* Philox key of the GA's draws                   */

@@ -75,6 +75,9 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int]
         L.jref_ga_step.restype = ctypes.c_int
+        L.jref_true_class.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int64, ctypes.c_void_p]
+        L.jref_true_class.restype = ctypes.c_int
         L.jref_trace_run.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                      ctypes.c_void_p, ctypes.c_int,
@@ -222,3 +225,19 @@ def ga_step(pop: np.ndarray, fit: np.ndarray, t: int, generation: int, c: int = 
     if rc != 0:
         raise ValueError(f"oracle rejected arguments (rc={rc})")
     return nxt, nfit
+
+
+TRUE_CAPPED = -2
+
+
+def true_class(genomes: np.ndarray, t: int, c: int = 8, grid: int = 16,
+               cap: int = 1 << 20) -> np.ndarray:
+    """Exhaustive true class of each genome: records with cls DET (size, hash
+    of the only terminal shape), ND_SITE (not deterministic) or TRUE_CAPPED;
+    steps = states visited."""
+    g = np.ascontiguousarray(genomes, dtype=np.uint64)
+    out = np.zeros(g.shape[0], dtype=RECORD)
+    rc = lib().jref_true_class(g.ctypes.data, g.shape[0], t, c, grid, cap, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
