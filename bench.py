@@ -114,6 +114,134 @@ def cpu_baseline(threads):
                       f"{dt:.1f} s wall on {threads} threads)"}
 
 
+# Scoring work per genome of t tiles (flops): the layer-1 gather (4t rows of
+# 256 added), the 256 x 256 layer and the 256 x 4 head.
+def score_flops(t):
+    return 4 * t * 256 + 2 * 256 * 256 + 2 * 256 * 4
+
+
+BF16_PEAK = 2.5e15
+
+
+def surrogate_path(args, jt, torch, batch, out, stream, timed, verify):
+    """Plain S_{2,8} classification preceded by the surrogate: score every
+    genotype, order the queue by predicted cost, classify in that order.
+    The network is trained first (untimed) on exact classifications of
+    one- and three-tile genotypes at G = 16 (a uniform three-tile sample and
+    all of S_{1,8}); no two-tile genotype, so none of the timed ones, is in
+    its training set."""
+    import numpy as np
+    from tests import inputs
+    dev = out.device
+    ntrain3 = 1 << 20
+    g3 = torch.from_numpy(inputs.three_tile_sample(ntrain3).view(np.int64)).to(dev)
+    g1 = torch.arange(4096, dtype=torch.int64, device=dev)
+    with jt.Batch(ntrain3) as b:
+        lab3 = b.classify(g3, 3, C, GRID, RUNS, SEED)
+        lab1 = b.classify(g1, 1, C, GRID, RUNS, SEED)
+    gt = torch.cat([g3, g1])
+    tt = torch.cat([torch.full((ntrain3,), 3, dtype=torch.uint8, device=dev),
+                    torch.full((4096,), 1, dtype=torch.uint8, device=dev)])
+    lab = torch.cat([lab3, lab1])
+    perm = torch.randperm(gt.shape[0], generator=torch.Generator().manual_seed(3)).to(dev)
+    gt, tt, lab = gt[perm].contiguous(), tt[perm].contiguous(), lab[perm].contiguous()
+    net = jt.MLP(4096)
+    net.init(1)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    steps = 2 * gt.shape[0] // 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        lo = (k * 4096) % (gt.shape[0] - 4096)
+        net.train_step(gt[lo:lo + 4096], tt[lo:lo + 4096], lab[lo:lo + 4096], lr=1e-3,
+                       loss=loss)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del g3, lab3, gt, tt, lab
+
+    genomes = torch.arange(TOTAL, dtype=torch.int64, device=dev)
+    scores = torch.empty(TOTAL, dtype=torch.float32, device=dev)
+    order = torch.empty(TOTAL, dtype=torch.int32, device=dev)
+    work = torch.empty(int(jt.lib().jatam_order_work_words(TOTAL)), dtype=torch.int32,
+                       device=dev)
+
+    def step():
+        net.score(genomes, T, out=scores, stream=stream)
+        jt.order_by_cost(scores, order=order, work=work, stream=stream)
+        batch.classify_range_ordered(0, TOTAL, order, T, C, GRID, RUNS, SEED, out=out,
+                                     stream=stream)
+
+    total_ms, _ = timed(step, step)
+    ok = verify()
+    # the scoring and ordering kernels alone
+    score_ms, _ = timed(lambda: net.score(genomes, T, out=scores, stream=stream),
+                        lambda: net.score(genomes, T, out=scores, stream=stream))
+    order_ms, _ = timed(lambda: jt.order_by_cost(scores, order=order, work=work, stream=stream),
+                        lambda: jt.order_by_cost(scores, order=order, work=work, stream=stream))
+    net.close()
+    score_s = score_ms / args.steps / 1e3
+    flops = TOTAL * score_flops(T)
+    return {"value": TOTAL * args.steps / (total_ms / 1e3),
+            "ms_per_step": total_ms / args.steps, "bit_exact": ok,
+            "score_ms": score_s * 1e3, "order_ms": order_ms / args.steps,
+            "score_genomes_per_s": TOTAL / score_s,
+            "score_roofline": {"bound": "mfma", "achieved": flops / score_s / 1e12,
+                               "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                               "frac": flops / score_s / BF16_PEAK,
+                               "kernel": "mlp_score_persistent_kernel<2>",
+                               "flops_per_genome": score_flops(T)},
+            "train_s": train_s, "train_steps": steps, "final_batch_loss": float(loss.item()),
+            "train_data": "exact classifications at G=16 of 2^20 uniform three-tile "
+                          "genotypes and all of S_1,8 (no two-tile genotype)",
+            "kernel": "score (bf16 MFMA) -> order by predicted cost (256-bucket counting "
+                      "sort) -> pipelined classification in that queue order"}
+
+
+def misclass_report(args, jt, torch):
+    """The classifier's error against the true class over all of S_{2,8}
+    (G=16, seed 1): the true class of every genotype (every growth order
+    followed), then the R-run classification for R = 1..20; a genotype the
+    R runs call DET that is not truly deterministic is misclassified.  Prints
+    one JSON line."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    piece = 1 << 22
+    true_det = torch.empty(TOTAL, dtype=torch.bool, device=dev)
+    counts = {"det": 0, "nd": 0, "undecided": 0, "explored": 0, "max_states": 0}
+    cap = 1 << 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with jt.Truth(piece, max_level=4096, waves=256) as tw:
+        for lo in range(0, TOTAL, piece):
+            rec = tw.true_class_range(lo, piece, T, C, GRID, cap=cap, stream=stream)
+            cls = rec[:, 0]
+            true_det[lo:lo + piece] = cls == 3
+            counts["det"] += int((cls == 3).sum())
+            counts["nd"] += int((cls == 1).sum())
+            counts["undecided"] += int((cls == -2).sum())
+            counts["explored"] += int((rec[:, 3] > 0).sum())
+            counts["max_states"] = max(counts["max_states"], int(rec[:, 3].max()))
+    torch.cuda.synchronize()
+    truth_s = time.perf_counter() - t0
+    out = torch.empty((TOTAL, 4), dtype=torch.int32, device=dev)
+    curve = []
+    with jt.Batch(TOTAL) as b:
+        for r in range(1, 21):
+            b.classify_range(0, TOTAL, T, C, GRID, r, SEED, out=out, stream=stream)
+            det = out[:, 0] == 3
+            curve.append({"R": r, "det": int(det.sum()),
+                          "misclassified": int((det & ~true_det).sum()),
+                          "missed_true_det": int((true_det & ~det).sum())})
+    line = {"metric": "S_2,8 genotypes classed DET by R runs that are not truly deterministic "
+                      "(G=16, seed 1)",
+            "unit": "genotypes", "n_gpus": 1, "genotypes": TOTAL,
+            "true_class": dict(counts, cap=cap, seconds=truth_s,
+                               genotypes_per_s=TOTAL / truth_s),
+            "curve": curve,
+            "data": "exhaustive enumeration of S_2,8"}
+    print(json.dumps(line), flush=True)
+
+
 def ga_report(args, jt, torch):
     """The surrogate-screened GA against the plain GA at an equal number of
     generations: three-tile genotypes, c=8, G=32, R=20, population 65,536,
@@ -226,8 +354,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = all usable cores, at most 16)")
-    ap.add_argument("--workload", choices=("enumeration", "ga"), default="enumeration",
-                    help="ga: the surrogate-screened GA report instead of the benchmark")
+    ap.add_argument("--workload", choices=("enumeration", "ga", "misclass"),
+                    default="enumeration",
+                    help="ga: the surrogate-screened GA report; misclass: the classifier's "
+                         "error against the true class over S_2,8, R = 1..20")
     ap.add_argument("--generations", type=int, default=500)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 blits and 4 elementwise copies of 256 MiB "
@@ -248,6 +378,9 @@ def main():
     jt.lib()
     if args.workload == "ga":
         ga_report(args, jt, torch)
+        return
+    if args.workload == "misclass":
+        misclass_report(args, jt, torch)
         return
     if args.copy_calibration:
         # a blit (copy_) and an elementwise kernel (neg), each reading and
@@ -344,6 +477,12 @@ def main():
     graph_value = TOTAL * args.steps / (graph_total_ms / 1e3)
     graph_batch.close()
 
+    # batched + surrogate path: the network (trained untimed, on genotypes
+    # that are not timed) scores every genotype, the queue is ordered by the
+    # predicted cost, and the pipeline takes the range in that order; scoring
+    # and ordering are inside the timed step
+    sur = surrogate_path(args, jt, torch, batch, out, stream, timed, verify)
+
     # batched path: one call per step, stage events recorded by the library
     batch.set_timing(True)
     batched_total_ms, _ = timed(batched_step, batched_step)
@@ -378,11 +517,12 @@ def main():
                    "genotypes_per_step": TOTAL, "t": T, "c": C, "grid": GRID, "runs": RUNS,
                    "seed": SEED, "tuning": tuning,
                    "autotune_ms": [round(ms, 4) for _, ms in tune_log]},
-        "bit_exact": bool(bit_exact),
+        "bit_exact": bool(bit_exact and sur["bit_exact"]),
         "paths": {
             "batched": {"value": batched_value, "ms_per_step": batched_total_ms / args.steps,
                         "bit_exact": batched_ok, "surrogate": False,
                         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
+            "surrogate": sur,
             "graph": {"value": graph_value, "ms_per_step": graph_total_ms / args.steps,
                       "bit_exact": graph_ok, "tuning": graph_tuning,
                       "kernel": "one captured 2^20-genotype slice pipeline, 16 hipGraph replays"},

@@ -266,6 +266,29 @@ typedef struct {
 } jatam_tuning_t;
 
 /*
+ * jatam_batch_classify_range with a queue order: queue position p holds
+ * genotype first + order[p] (order: device uint32[n], a permutation of
+ * 0..n-1; an entry >= n is skipped).  Records stay indexed by genotype and
+ * never depend on the order.  The order is how a cost prediction (e.g.
+ * jatam_order_by_cost over surrogate scores) reaches the first-run queue.
+ */
+int jatam_batch_classify_range_ordered(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
+                                       int c, int grid_limit, int runs, uint64_t seed,
+                                       const uint32_t* order, jatam_result_t* out,
+                                       uint64_t* tally, void* stream);
+
+/*
+ * A queue order by predicted cost: order[0..n) lists 0..n-1 by descending
+ * score, in 256 buckets of 16 log2(score + 2) (scores as jatam_mlp_score
+ * gives them, the expected size of a deterministic structure; NaN last),
+ * items of one bucket in no particular order.  work: device scratch of
+ * jatam_order_work_words(n) uint32 words.  n < 2^32.
+ */
+int64_t jatam_order_work_words(int64_t n);
+int jatam_order_by_cost(const float* scores, int64_t n, uint32_t* order, uint32_t* work,
+                        void* stream);
+
+/*
  * The batch classification of the problem statement (App. B.2: a tile set in,
  * its classified phenotype out) over a mixed stream in one call.
  *   batch   workspace from jatam_batch_create, n <= its max_n
@@ -508,6 +531,48 @@ int jatam_shape_histogram(const jatam_result_t* recs, int64_t n, jatam_shape_cou
 int jatam_classify_static(const uint64_t* genotypes, int64_t n, int t, int c, int grid_limit,
                           int runs, uint64_t seed, jatam_result_t* out, uint64_t* tally,
                           void* stream);
+
+/* ------------------------------------------------------------------------
+ * True class (§3.2, §4.1): the k runs of the classifier sample growth
+ * orders and can miss an order that meets an ambiguous site or ends in
+ * another shape, so a genotype they class DET may not be deterministic; the
+ * paper measures how often as k grows.  These calls follow every order:
+ *   cls  JATAM_DET      every order ends in one shape without an event;
+ *                       size and hash of that shape
+ *        JATAM_ND_SITE  some order meets an event (a bondable site outside
+ *                       the box, or an ambiguous site) or ends in a second
+ *                       shape (occupancy compared without rotation); size 0,
+ *                       hash 0
+ *        JATAM_UNDECIDED  the search would pass `cap` states (or a level
+ *                       would pass the workspace's max_level); size 0, hash 0
+ *        JATAM_INVALID  genome bits above 4*t*log2(c)
+ *   steps  states explored (0 when one run decided: an event in it, no
+ *          choice in it, or a guarded shape, whose every order places the
+ *          same tiles).
+ * The verdict does not depend on the order in which states are visited
+ * (except where the search is cut off by cap).
+ * ------------------------------------------------------------------------ */
+enum { JATAM_UNDECIDED = -2 };
+
+typedef struct jatam_truth jatam_truth_t;
+
+/* Workspace for calls of up to max_n genotypes: the queue of genotypes one
+ * run leaves open, and per exploring wave (waves in [1, 4096]) two levels of
+ * max_level states (max_level in [1, 2^18]; 644 bytes per state) and a hash
+ * table of 2 * max_level slots.  Allocates and zeroes device memory
+ * (synchronises the device). */
+int jatam_truth_create(int64_t max_n, int32_t max_level, int32_t waves, jatam_truth_t** out);
+int jatam_truth_destroy(jatam_truth_t* w);
+
+/* True class of n genotypes (device array) of t tiles on a grid of side
+ * grid_limit; cap >= 1 limits the states explored per genotype.  out:
+ * device, n records.  Calls on one workspace must be serialised (one
+ * stream). */
+int jatam_true_class(jatam_truth_t* w, const uint64_t* genotypes, int64_t n, int t, int c,
+                     int grid_limit, int64_t cap, jatam_result_t* out, void* stream);
+/* Same for the range genome_i = first + i. */
+int jatam_true_class_range(jatam_truth_t* w, uint64_t first, int64_t n, int t, int c,
+                           int grid_limit, int64_t cap, jatam_result_t* out, void* stream);
 
 /* Static description of an error code. */
 const char* jatam_strerror(int code);

@@ -319,6 +319,43 @@ int jatam_batch_classify_range(jatam_batch_t* batch, uint64_t first, int64_t n, 
     return launch_timed(batch, a, grid_limit, t, (hipStream_t)stream);
 }
 
+int jatam_batch_classify_range_ordered(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
+                                       int c, int grid_limit, int runs, uint64_t seed,
+                                       const uint32_t* order, jatam_result_t* out,
+                                       uint64_t* tally, void* stream)
+{
+    jatam::Params p;
+    int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
+    if (rc != JATAM_OK)
+        return rc;
+    if ((rc = batch_check(batch, n, out)) != JATAM_OK)
+        return rc;
+    if (n > 0) {
+        const uint64_t last = first + (uint64_t)(n - 1);
+        if (last < first || (p.genome_bits < 64 && (last >> p.genome_bits) != 0) ||
+            order == nullptr)
+            return JATAM_E_INVALID_ARG;
+    }
+    jatam::BatchArgs a = batch_args(batch, p, n, out, tally);
+    a.first = first;
+    a.order = order;
+    return launch_timed(batch, a, grid_limit, t, (hipStream_t)stream);
+}
+
+int64_t jatam_order_work_words(int64_t n)
+{
+    return n < 0 ? -1 : (int64_t)jatam::order_work_words((uint64_t)n);
+}
+
+int jatam_order_by_cost(const float* scores, int64_t n, uint32_t* order, uint32_t* work,
+                        void* stream)
+{
+    if (n < 0 || n > ((int64_t)1 << 32) - 1 ||
+        (n > 0 && (scores == nullptr || order == nullptr || work == nullptr)))
+        return JATAM_E_INVALID_ARG;
+    return jatam::launch_order_by_cost(scores, (uint32_t)n, order, work, (hipStream_t)stream);
+}
+
 int jatam_batch_classify_items(jatam_batch_t* batch, const jatam_item_t* items, int64_t n,
                                int c, int runs, uint64_t seed, jatam_result_t* out,
                                uint64_t* tally, void* stream)

@@ -237,6 +237,38 @@ int launch_select_top(const float* scores, uint32_t n, uint32_t k, uint32_t* out
 int launch_gather(const uint64_t* src, const uint32_t* idx, uint32_t n, uint64_t* dst,
                   hipStream_t s);
 
+// Queue order by predicted cost (descending score buckets) into order[n];
+// work: order_work_words(n) words of device scratch.
+uint64_t order_work_words(uint64_t n);
+int launch_order_by_cost(const float* scores, uint32_t n, uint32_t* order, uint32_t* work,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// True class by exhaustive exploration (jatam_truth.hip).
+// ---------------------------------------------------------------------------
+struct TruthArgs {
+    const uint64_t* genomes;        // list mode, or nullptr: genome i = first + i
+    uint64_t first;
+    int64_t n;
+    int t, c, bits, genome_bits, grid;
+    uint32_t key0, key1;            // key of the one run of the first stage
+    int64_t cap;                    // most states explored per genotype
+    jatam_result_t* out;
+    uint32_t* counters;             // [0] queued genotypes, [1] next one to explore
+    uint32_t* queue;                // [n]
+    uint32_t max_level;             // states per level (<= 2^18)
+    int table_log2;                 // slots of each wave's table (>= 2 * max_level)
+    uint32_t* arena;                // per wave: 2 levels of max_level states
+    uint32_t* lists;                // per wave: max_level
+    uint32_t* terms;                // per wave: max_level
+    unsigned long long* tables;     // per wave: 2^table_log2, all zero between calls
+};
+
+// Words of one stored state in the exploration (occupancy, tiles, hash).
+constexpr int truth_state_words(int W) { return W * W / 32 + W * W / 8 + 1; }
+constexpr uint32_t kMaxTruthLevel = 1u << 18;   // states per level (18-bit parent index)
+int launch_truth(const TruthArgs& a, int blocks, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Shape histogram.
 // ---------------------------------------------------------------------------

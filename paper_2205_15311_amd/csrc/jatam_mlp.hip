@@ -358,6 +358,190 @@ __global__ __launch_bounds__(256) void mlp_score_kernel(MlpArgs a, const uint64_
 }
 
 // ---------------------------------------------------------------------------
+// Persistent scoring: eight waves per workgroup, wave w owning hidden columns
+// 32w .. 32w+31 of both layers.  Its slices of W1, W2 and W3 are loaded into
+// registers once per launch as MFMA B operands, so a tile of 64 genomes
+// costs no weight traffic at all:
+//   layer 1   the one-hot input is a matrix like any other: each lane builds
+//             its A operand (8 bf16 of one edge's one-hot row) from the
+//             genome in registers, x W1 in v_mfma_f32_16x16x32_bf16 (2 k
+//             blocks for two-tile genomes, 3 for three), + b1, ReLU, bf16
+//             -> h1 in LDS (the wave's 32 columns)
+//   layer 2   h1 (all 256 columns, from LDS) x the wave's W2 slice, + b2,
+//             ReLU, bf16 -> the wave's h2 columns in LDS
+//   head      the wave's 32 h2 columns x W3 rows 32w.. (one k block): a
+//             partial [64 x 4], summed over the 8 waves in wave order (so
+//             scores do not depend on timing), softmax, score
+// Two workgroup barriers per tile.  Rounding points as everywhere else: h1
+// and h2 in bf16, fp32 sums.
+// ---------------------------------------------------------------------------
+constexpr int kSc2Waves = 8;
+constexpr int kSc2Rows = 64;
+constexpr int kSc2Pitch = kMlpHidden + 8;   // bf16 per LDS row (16-lane reads conflict-free)
+
+// LDS writes of the wave before this point are seen by its reads after it
+// (a wave's LDS operations complete in order; only the compiler is held).
+__device__ __forceinline__ void mlp_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p)
+{
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+
+// One-hot A operand of k block kb for a genome: lane group q = l / 16 holds
+// edge e = 4 kb + q, so its 8 values are 1.0 at that edge's colour (none if
+// the edge is absent).
+__device__ __forceinline__ bf16x8 onehot_operand(uint64_t g, int t, int bits, uint32_t cmask,
+                                                 int e)
+{
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (e < 4 * t) {
+        const uint32_t colour = (uint32_t)(g >> (bits * (4 * t - 1 - e))) & cmask;
+        // colour < 8 for every c the network takes (its input has 8 slots per edge)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[q] = (colour == 2u * q ? 0x3F80u : 0u) | (colour == 2u * q + 1u ? 0x3F800000u : 0u);
+    }
+    bf16x8 v;
+    __builtin_memcpy(&v, w, sizeof(v));
+    return v;
+}
+
+template <int KB1>
+__global__ __launch_bounds__(512) void mlp_score_persistent_kernel(MlpArgs a,
+                                                                   const uint64_t* genomes,
+                                                                   const uint8_t* tvec, int t_all,
+                                                                   uint32_t n, float* scores)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t h1s[kSc2Rows][kSc2Pitch];
+    __shared__ __attribute__((aligned(16))) uint16_t h2s[kSc2Rows][kSc2Pitch];
+    __shared__ float part[kSc2Waves][kSc2Rows][kMlpOut];
+    const int tid = (int)threadIdx.x, wave = tid >> 6, l = tid & 63;
+    const int r16 = l & 15, q = l >> 4;
+    const int col0 = 32 * wave;
+    const uint32_t cmask = (uint32_t)a.c - 1u;
+    // the wave's weights, as B operands: lane holds B[8q + i][r16] of each block
+    bf16x8 w1f[KB1][2], w2f[8][2], w3f;
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            uint16_t v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                v[i] = a.w1b[(size_t)(32 * kb + 8 * q + i) * kMlpHidden + col0 + 16 * nb + r16];
+            __builtin_memcpy(&w1f[kb][nb], v, sizeof(v));
+        }
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            w2f[kb][nb] = load_bf16x8(a.w2t + (size_t)(col0 + 16 * nb + r16) * kMlpHidden +
+                                      32 * kb + 8 * q);
+    w3f = load_bf16x8(a.w3t + (size_t)r16 * kMlpHidden + col0 + 8 * q);
+    const float b1v[2] = {a.p.b1[col0 + r16], a.p.b1[col0 + 16 + r16]};
+    const float b2v[2] = {a.p.b2[col0 + r16], a.p.b2[col0 + 16 + r16]};
+    const float b3v = tid < kSc2Rows * kMlpOut ? a.p.b3[tid & 3] : 0.f;
+
+    const uint32_t tiles = (n + kSc2Rows - 1) / kSc2Rows;
+    for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint32_t s0 = tile * kSc2Rows;
+        // -- layer 1: one-hot x W1 ----------------------------------------
+        floatx4 acc[4][2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const uint32_t sidx = s0 + (uint32_t)(16 * mb + r16);
+            uint64_t g = 0;
+            int t = 0;
+            if (sidx < n) {
+                g = genomes[sidx];
+                t = mlp_tiles(tvec != nullptr ? tvec[sidx] : t_all);
+            }
+            acc[mb][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc[mb][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb) {
+                const bf16x8 x = onehot_operand(g, t, a.bits, cmask, 4 * kb + q);
+                acc[mb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, w1f[kb][0], acc[mb][0],
+                                                                     0, 0, 0);
+                acc[mb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, w1f[kb][1], acc[mb][1],
+                                                                     0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[mb][nb][i] + b1v[nb];
+                    h1s[16 * mb + 4 * q + i][col0 + 16 * nb + r16] = bf16_bits(z > 0.f ? z : 0.f);
+                }
+        __syncthreads();   // h1 complete; the previous tile's partial heads consumed
+        // -- layer 2: h1 x W2 (the wave's columns) ------------------------
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            acc[mb][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+            acc[mb][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) {
+                const bf16x8 af = load_bf16x8(&h1s[16 * mb + r16][32 * kb + 8 * q]);
+                acc[mb][0] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[kb][0], acc[mb][0], 0, 0, 0);
+                acc[mb][1] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[kb][1], acc[mb][1], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[mb][nb][i] + b2v[nb];
+                    h2s[16 * mb + 4 * q + i][col0 + 16 * nb + r16] = bf16_bits(z > 0.f ? z : 0.f);
+                }
+        mlp_wave_sync();   // the wave reads back only its own h2 columns
+        // -- head: the wave's partial h2 W3 -------------------------------
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const bf16x8 af = load_bf16x8(&h2s[16 * mb + r16][col0 + 8 * q]);
+            const floatx4 o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                af, w3f, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            if (r16 < kMlpOut)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    part[wave][16 * mb + 4 * q + i][r16] = o[i];
+        }
+        __syncthreads();   // partial heads complete; h1 free for the next tile
+        if (tid < kSc2Rows * kMlpOut) {
+            const int row = tid >> 2, o = tid & 3;
+            float v = 0.f;
+#pragma unroll
+            for (int w = 0; w < kSc2Waves; ++w)
+                v += part[w][row][o];
+            v += b3v;
+            // gather the row's four outputs in its lane quad
+            const float o0 = __shfl(v, (l & ~3) + 0), o1 = __shfl(v, (l & ~3) + 1);
+            const float o2 = __shfl(v, (l & ~3) + 2), o3 = __shfl(v, (l & ~3) + 3);
+            if (o == 0 && s0 + (uint32_t)row < n) {
+                const float mx = fmaxf(o0, fmaxf(o1, o2));
+                const float e0 = expf(o0 - mx), e1 = expf(o1 - mx), e2 = expf(o2 - mx);
+                scores[s0 + row] = e2 / (e0 + e1 + e2) * expf(o3) - 1.f;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Head and loss: out = h2 W3 + b3 per sample; with labels, the per-sample loss
 // and dout = d(mean loss)/d(out).
 // ---------------------------------------------------------------------------
@@ -628,8 +812,29 @@ int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* t
 {
     if (n == 0)
         return JATAM_OK;
-    hipLaunchKernelGGL(mlp_score_kernel, dim3((n + kScoreRows - 1) / kScoreRows), dim3(256), 0, s,
-                       a, genomes, tvec, t_all, n, scores);
+    // k blocks of the one-hot input that can be nonzero: 4 edges per block
+    const int kb1 = tvec != nullptr ? 3 : t_all;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return JATAM_E_HIP;
+    const void* fn = kb1 == 1   ? (const void*)mlp_score_persistent_kernel<1>
+                     : kb1 == 2 ? (const void*)mlp_score_persistent_kernel<2>
+                                : (const void*)mlp_score_persistent_kernel<3>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, 0) != hipSuccess)
+        return JATAM_E_HIP;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const uint32_t tiles = (n + kSc2Rows - 1) / kSc2Rows;
+    const uint32_t blocks = tiles < (uint32_t)(cus * per_cu) ? tiles : (uint32_t)(cus * per_cu);
+    if (kb1 == 1)
+        hipLaunchKernelGGL(mlp_score_persistent_kernel<1>, dim3(blocks), dim3(512), 0, s, a,
+                           genomes, tvec, t_all, n, scores);
+    else if (kb1 == 2)
+        hipLaunchKernelGGL(mlp_score_persistent_kernel<2>, dim3(blocks), dim3(512), 0, s, a,
+                           genomes, tvec, t_all, n, scores);
+    else
+        hipLaunchKernelGGL(mlp_score_persistent_kernel<3>, dim3(blocks), dim3(512), 0, s, a,
+                           genomes, tvec, t_all, n, scores);
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 

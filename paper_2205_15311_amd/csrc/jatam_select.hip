@@ -196,4 +196,110 @@ int launch_select_top(const float* scores, uint32_t n, uint32_t k, uint32_t* out
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// Queue order by predicted cost: a counting sort of n scores into 256
+// buckets, highest cost first.  Blocks of kOrderBlock items histogram their
+// buckets (bucket-major: entry b * nblocks + block), one exclusive scan of
+// the histogram gives every (bucket, block) its first queue position, and
+// each block scatters its items from there with LDS cursors.  Items of one
+// bucket keep no particular order among themselves (the classification's
+// records never depend on the queue order).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOrderBlock = 4096;
+
+// Bucket of a score (expected DET size P(DET) e^pred - 1, at least -1):
+// 16 log2(score + 2) clamped to 0..255, reversed so that high costs come
+// first; NaN last.
+__device__ __forceinline__ uint32_t cost_bucket(float score)
+{
+    if (!(score == score))
+        return 255u;
+    const float v = 16.f * __log2f(fmaxf(score, -1.f) + 2.f);
+    const uint32_t q = v < 0.f ? 0u : v > 255.f ? 255u : (uint32_t)v;
+    return 255u - q;
+}
+
+__global__ __launch_bounds__(256) void order_hist_kernel(const float* __restrict__ scores,
+                                                         uint32_t n, uint32_t* hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t lo = blockIdx.x * kOrderBlock, hi = min(n, lo + kOrderBlock);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256)
+        atomicAdd(&h[cost_bucket(scores[i])], 1u);
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// In-place exclusive scan of m words, in three passes (per-1024 blocks,
+// their totals, the block offsets added back).
+__global__ __launch_bounds__(1024) void order_scan_block_kernel(uint32_t* x, uint32_t m,
+                                                                uint32_t* sums)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t v = i < m ? x[i] : 0u;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (i < m)
+        x[i] = part[threadIdx.x] - v;
+    if (threadIdx.x == 1023)
+        sums[blockIdx.x] = part[1023];
+}
+
+__global__ __launch_bounds__(1024) void order_scan_add_kernel(uint32_t* x, const uint32_t* sums,
+                                                              uint32_t m)
+{
+    const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+    if (i < m)
+        x[i] += sums[blockIdx.x];
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const float* __restrict__ scores,
+                                                            uint32_t n, const uint32_t* hist,
+                                                            uint32_t* order)
+{
+    __shared__ uint32_t cursor[256];
+    cursor[threadIdx.x] = hist[threadIdx.x * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const uint32_t lo = blockIdx.x * kOrderBlock, hi = min(n, lo + kOrderBlock);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256)
+        order[atomicAdd(&cursor[cost_bucket(scores[i])], 1u)] = i;
+}
+
+uint64_t order_work_words(uint64_t n)
+{
+    const uint64_t m = 256 * ((n + kOrderBlock - 1) / kOrderBlock);
+    return m + (m + 1023) / 1024 + 1;
+}
+
+int launch_order_by_cost(const float* scores, uint32_t n, uint32_t* order, uint32_t* work,
+                         hipStream_t s)
+{
+    if (n == 0)
+        return JATAM_OK;
+    const uint32_t nb = (n + kOrderBlock - 1) / kOrderBlock;
+    const uint32_t m = 256 * nb;
+    uint32_t* hist = work;
+    uint32_t* sums = work + m;
+    const uint32_t sb = (m + 1023) / 1024;
+    hipLaunchKernelGGL(order_hist_kernel, dim3(nb), dim3(256), 0, s, scores, n, hist);
+    hipLaunchKernelGGL(order_scan_block_kernel, dim3(sb), dim3(1024), 0, s, hist, m, sums);
+    // the block totals: at most 1024 of them for n up to 2^24 items, more in
+    // a second level
+    if (sb > 1) {
+        hipLaunchKernelGGL(select_scan_sums_kernel, dim3(1), dim3(1024), 0, s, sums, sb);
+        hipLaunchKernelGGL(order_scan_add_kernel, dim3(sb), dim3(1024), 0, s, hist, sums, m);
+    }
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(nb), dim3(256), 0, s, scores, n, hist, order);
+    return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
+}
+
 }  // namespace jatam

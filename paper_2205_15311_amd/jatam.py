@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjatam.so")
 
-UNBOUND, ND_SITE, ND_RUNS, DET, INVALID = 0, 1, 2, 3, -1
+UNBOUND, ND_SITE, ND_RUNS, DET, INVALID, UNDECIDED = 0, 1, 2, 3, -1, -2
 CLASS_NAMES = {UNBOUND: "UNBOUND", ND_SITE: "ND_SITE", ND_RUNS: "ND_RUNS", DET: "DET",
                INVALID: "INVALID"}
 E_INVALID_ARG, E_UNSUPPORTED, E_HIP = -1, -2, -3
@@ -121,6 +121,21 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
         L.jatam_shape_histogram.restype = i32
+        L.jatam_batch_classify_range_ordered.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64,
+                                                         vp, vp, vp, vp]
+        L.jatam_batch_classify_range_ordered.restype = i32
+        L.jatam_order_work_words.argtypes = [i64]
+        L.jatam_order_work_words.restype = i64
+        L.jatam_order_by_cost.argtypes = [vp, i64, vp, vp, vp]
+        L.jatam_order_by_cost.restype = i32
+        L.jatam_truth_create.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp)]
+        L.jatam_truth_create.restype = i32
+        L.jatam_truth_destroy.argtypes = [vp]
+        L.jatam_truth_destroy.restype = i32
+        L.jatam_true_class.argtypes = [vp, vp, i64, i32, i32, i32, i64, vp, vp]
+        L.jatam_true_class.restype = i32
+        L.jatam_true_class_range.argtypes = [vp, u64, i64, i32, i32, i32, i64, vp, vp]
+        L.jatam_true_class_range.restype = i32
         _lib = L
     return _lib
 
@@ -198,6 +213,28 @@ def classify_static(genotypes: torch.Tensor, t: int, c: int = 8, grid_limit: int
                                      _stream_handle(stream))
     _check(rc, "jatam_classify_static")
     return rec
+
+
+def order_by_cost(scores: torch.Tensor, order: torch.Tensor | None = None,
+                  work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """jatam_order_by_cost: a queue order (int32 tensor, a permutation of
+    0..n-1) by descending score bucket.  `work` (int32, at least
+    jatam_order_work_words(n) elements) may be passed to avoid allocating."""
+    if scores.dtype != torch.float32 or scores.dim() != 1 or not scores.is_cuda \
+            or not scores.is_contiguous():
+        raise ValueError("scores must be a contiguous 1-D float32 device tensor")
+    n = scores.shape[0]
+    words = int(lib().jatam_order_work_words(n))
+    if order is None:
+        order = torch.empty(n, dtype=torch.int32, device=scores.device)
+    if work is None:
+        work = torch.empty(max(words, 1), dtype=torch.int32, device=scores.device)
+    if order.numel() != n or work.numel() < words:
+        raise ValueError("order must hold n entries and work the scratch words")
+    rc = lib().jatam_order_by_cost(scores.data_ptr(), n, order.data_ptr(), work.data_ptr(),
+                                   _stream_handle(stream))
+    _check(rc, "jatam_order_by_cost")
+    return order
 
 
 def records_to_numpy(rec: torch.Tensor):
@@ -313,6 +350,55 @@ def make_items(genomes, t, grid, rng_ids=None):
     return arr.view(np.uint8).reshape(n, ITEM_BYTES)
 
 
+class Truth:
+    """A jatam_truth_t workspace and the true-class calls (every growth order
+    followed): records (n, 4) int32 [cls, size, hash bits, states], cls one
+    of DET, ND_SITE, UNDECIDED (past `cap` states) or INVALID."""
+
+    def __init__(self, max_n: int, max_level: int = 4096, waves: int = 64):
+        handle = ctypes.c_void_p()
+        _check(lib().jatam_truth_create(int(max_n), int(max_level), int(waves),
+                                        ctypes.byref(handle)), "jatam_truth_create")
+        self._h = handle
+        self.max_n = int(max_n)
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().jatam_truth_destroy(self._h), "jatam_truth_destroy")
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def true_class(self, genotypes: torch.Tensor, t: int, c: int = 8, grid_limit: int = 16,
+                   cap: int = 1 << 20, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+        """jatam_true_class over a device genome array."""
+        if genotypes.dtype not in (torch.int64, torch.uint64) or genotypes.dim() != 1:
+            raise ValueError("genotypes must be a 1-D int64/uint64 tensor")
+        if not genotypes.is_cuda or not genotypes.is_contiguous():
+            raise ValueError("genotypes must be a contiguous device tensor")
+        n = genotypes.shape[0]
+        rec = _records(n, genotypes.device, out)
+        rc = lib().jatam_true_class(self._h, genotypes.data_ptr(), n, t, c, grid_limit, cap,
+                                    rec.data_ptr(), _stream_handle(stream))
+        _check(rc, "jatam_true_class")
+        return rec
+
+    def true_class_range(self, first: int, n: int, t: int, c: int = 8, grid_limit: int = 16,
+                         cap: int = 1 << 20, out: torch.Tensor | None = None, device="cuda",
+                         stream=None) -> torch.Tensor:
+        """jatam_true_class_range: genome i = first + i."""
+        rec = _records(n, device, out)
+        rc = lib().jatam_true_class_range(self._h, first, n, t, c, grid_limit, cap,
+                                          rec.data_ptr(), _stream_handle(stream))
+        _check(rc, "jatam_true_class_range")
+        return rec
+
+
 class Batch:
     """A jatam_batch_t workspace (device queues for up to max_n genotypes per
     call) and the pipelined calls that use it."""
@@ -374,6 +460,24 @@ class Batch:
                                               rec.data_ptr(), self._tally_ptr(tally),
                                               _stream_handle(stream))
         _check(rc, "jatam_batch_classify_range")
+        return rec
+
+    def classify_range_ordered(self, first: int, n: int, order: torch.Tensor, t: int,
+                               c: int = 8, grid_limit: int = 16, runs: int = 20, seed: int = 1,
+                               out: torch.Tensor | None = None,
+                               tally: torch.Tensor | None = None, device="cuda",
+                               stream=None) -> torch.Tensor:
+        """jatam_batch_classify_range_ordered: queue position p holds genotype
+        first + order[p] (order: int32 device tensor of n entries)."""
+        if order.dtype != torch.int32 or order.numel() != n or not order.is_cuda \
+                or not order.is_contiguous():
+            raise ValueError("order must be a contiguous int32 device tensor of n entries")
+        rec = _records(n, device, out)
+        rc = lib().jatam_batch_classify_range_ordered(self._h, first, n, t, c, grid_limit, runs,
+                                                      seed, order.data_ptr(), rec.data_ptr(),
+                                                      self._tally_ptr(tally),
+                                                      _stream_handle(stream))
+        _check(rc, "jatam_batch_classify_range_ordered")
         return rec
 
     def classify_items(self, items: torch.Tensor, c: int = 8, runs: int = 20, seed: int = 1,

@@ -123,3 +123,19 @@ def test_screen_struct_matches_the_header():
     from paper_2205_15311_amd import jatam
     assert [f for f, _ in jatam.ScreenStruct._fields_] == struct_fields("jatam_screen_t")
     assert ct.sizeof(jatam.ScreenStruct) == 24
+
+
+def test_true_class_rejects_bad_arguments(lib):
+    """The true-class calls validate before touching a workspace."""
+    out = ctypes.create_string_buffer(16)
+    g = ctypes.c_uint64(0)
+    h = ctypes.c_void_p()
+    # no workspace; bad create arguments
+    assert lib.jatam_true_class(None, ctypes.addressof(g), 1, 2, 8, 16, 100, out, None) == -1
+    assert lib.jatam_true_class_range(None, 0, 1, 2, 8, 16, 100, out, None) == -1
+    assert lib.jatam_truth_create(0, 16, 1, ctypes.byref(h)) == -1
+    assert lib.jatam_truth_create(16, 0, 1, ctypes.byref(h)) == -1
+    assert lib.jatam_truth_create(16, (1 << 18) + 1, 1, ctypes.byref(h)) == -1
+    assert lib.jatam_truth_create(16, 16, 0, ctypes.byref(h)) == -1
+    assert lib.jatam_truth_create(16, 16, 1, None) == -1
+    assert lib.jatam_truth_destroy(None) == 0

@@ -146,19 +146,61 @@ def test_queue_order_does_not_change_records(jt):
 
 
 def test_surrogate_cost_order_keeps_records(jt):
-    """The queue ordered by the surrogate's predicted cost (log1p size, most
-    expensive first): records equal the oracle's."""
+    """The queue ordered by an (untrained) surrogate's predicted cost, most
+    expensive first: records equal the oracle's."""
     n = 1 << 15
     g, t, grid, items = mixed_items(jt, n)
     dg = torch.from_numpy(g.view(np.int64)).cuda()
     dt = torch.from_numpy(t.astype(np.uint8)).cuda()
     with jt.MLP(4096) as net, jt.Batch(n) as b:
         net.init(5)
-        cost = net.forward(dg, dt)[:, 3]
-        order = torch.argsort(cost, descending=True).to(torch.int32).contiguous()
+        order = jt.order_by_cost(net.score(dg, dt))
         dev = torch.from_numpy(jt.make_items(g, t, grid)).cuda()
         got = records(b.classify_items(dev, 8, 20, 1, order=order))
     assert_same(got, ref.classify_items(items), "surrogate order")
+
+
+def spearman(a, b):
+    ra = np.argsort(np.argsort(a, kind="stable"), kind="stable").astype(np.float64)
+    rb = np.argsort(np.argsort(b, kind="stable"), kind="stable").astype(np.float64)
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+def test_trained_cost_order_follows_the_exact_work(jt):
+    """A network trained on exact classifications orders a range of S_{2,8}
+    it has not seen by its exact work: the order is a permutation whose
+    score buckets never rise, the ordered pipeline gives the oracle's
+    records, and the predicted cost ranks genotypes by their exact placement
+    count (Spearman) far better than the untrained network's."""
+    rng = np.random.default_rng(12)
+    train = rng.integers(0, 1 << 23, size=1 << 17, dtype=np.uint64)   # lower half of S_2,8
+    dtrain = torch.from_numpy(train.view(np.int64)).cuda()
+    lab = jt.classify(dtrain, 2, 8, 16, 20, 1)
+    first, n = 3 << 22, 1 << 15                                        # upper half
+    want = ref.classify_range(first, n, 2, grid=16, runs=20, seed=1)
+    genomes = torch.arange(first, first + n, dtype=torch.int64, device="cuda")
+    corr = {}
+    with jt.MLP(4096) as net, jt.Batch(n) as b:
+        net.init(7)
+        corr["untrained"] = spearman(net.score(genomes, 2).cpu().numpy(), want["steps"])
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for step in range(400):
+            lo = (step * 4096) % (1 << 17)
+            net.train_step(dtrain[lo:lo + 4096], 2, lab[lo:lo + 4096], lr=1e-3, loss=loss)
+        scores = net.score(genomes, 2)
+        order = jt.order_by_cost(scores)
+        got = records(b.classify_range_ordered(first, n, order, 2, 8, 16, 20, 1))
+        sc = scores.cpu().numpy()
+        o = order.cpu().numpy().astype(np.int64)
+    assert_same(got, want, "trained cost order")
+    assert np.array_equal(np.sort(o), np.arange(n))
+    # buckets of 16 log2(score + 2), never rising along the order (the kernel's
+    # fast log2 may put a score on a bucket boundary one bucket off)
+    key = np.floor(16 * np.log2(np.maximum(sc[o], -1.0) + 2.0)).clip(0, 255)
+    assert np.all(np.diff(key) <= 1) and np.sum(np.diff(key) > 0) <= n // 100
+    corr["trained"] = spearman(sc, want["steps"])
+    print("Spearman(score, exact steps):", corr)
+    assert corr["trained"] > 0.5 and corr["trained"] > corr["untrained"] + 0.2, corr
 
 
 @pytest.mark.parametrize("t,grid", [(3, 32), (2, 32), (3, 24), (4, 20)])
