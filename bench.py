@@ -99,19 +99,45 @@ def profiled_traffic(kernel):
     return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(threads):
-    """The oracle, as it stands, on a strided 1/16 sample of S_{2,8}."""
+    """The oracle, as it stands (gcc -O3), over the whole of S_{2,8} on
+    `threads` threads, checked against the golden per-slice digests; and on
+    one thread over a 1/64 sample spread over the space (genotype
+    i * 2654435761 mod 2^24, a bijection of the space since the multiplier
+    is odd, for i < 2^18)."""
     import numpy as np
     from oracle import ref
-    sample = (np.arange(TOTAL // 16, dtype=np.uint64) * np.uint64(16) + np.uint64(7))
-    ref.classify(sample[:4096], T, c=C, grid=GRID, runs=RUNS, seed=SEED, threads=threads)
+    with open(os.path.join(ROOT, "tests", "golden", "s28_digests.json")) as f:
+        gold = json.load(f)
+    ref.classify_range(0, 4096, T, c=C, grid=GRID, runs=RUNS, seed=SEED, threads=threads)
     t0 = time.perf_counter()
-    ref.classify(sample, T, c=C, grid=GRID, runs=RUNS, seed=SEED, threads=threads)
+    rec = ref.classify_range(0, TOTAL, T, c=C, grid=GRID, runs=RUNS, seed=SEED, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": len(sample) / dt, "unit": "genotypes/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"genotypes 16*i+7 of S_2,8, i < 2^20 ({len(sample)} genotypes, "
-                      f"{dt:.1f} s wall on {threads} threads)"}
+    ok = all(hashlib.sha256(rec[s["first"]:s["first"] + s["n"]].tobytes()).hexdigest()
+             == s["sha256"] for s in gold["slices"])
+    del rec
+    sample = (np.arange(TOTAL // 64, dtype=np.uint64) * np.uint64(2654435761)) \
+        & np.uint64(TOTAL - 1)
+    t1 = time.perf_counter()
+    ref.classify(sample, T, c=C, grid=GRID, runs=RUNS, seed=SEED, threads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": TOTAL / dt, "unit": "genotypes/s", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(), "matches_golden": bool(ok),
+            "sample": f"all of S_2,8 ({TOTAL} genotypes, {dt:.1f} s wall on {threads} threads)",
+            "one_thread": {"value": len(sample) / dt1, "unit": "genotypes/s",
+                           "sample": f"genotypes i*2654435761 mod 2^24 of S_2,8, i < 2^18 "
+                                     f"({len(sample)} genotypes, {dt1:.1f} s wall)"}}
 
 
 # Scoring work per genome of t tiles (flops): the layer-1 gather (4t rows of
@@ -166,7 +192,7 @@ def surrogate_path(args, jt, torch, batch, out, stream, timed, verify):
                        device=dev)
 
     def step():
-        net.score(genomes, T, out=scores, stream=stream)
+        net.predict(genomes, T, jt.PREDICT_COST, out=scores, stream=stream)
         jt.order_by_cost(scores, order=order, work=work, stream=stream)
         batch.classify_range_ordered(0, TOTAL, order, T, C, GRID, RUNS, SEED, out=out,
                                      stream=stream)
@@ -174,8 +200,10 @@ def surrogate_path(args, jt, torch, batch, out, stream, timed, verify):
     total_ms, _ = timed(step, step)
     ok = verify()
     # the scoring and ordering kernels alone
-    score_ms, _ = timed(lambda: net.score(genomes, T, out=scores, stream=stream),
-                        lambda: net.score(genomes, T, out=scores, stream=stream))
+    def score():
+        net.predict(genomes, T, jt.PREDICT_COST, out=scores, stream=stream)
+
+    score_ms, _ = timed(score, score)
     order_ms, _ = timed(lambda: jt.order_by_cost(scores, order=order, work=work, stream=stream),
                         lambda: jt.order_by_cost(scores, order=order, work=work, stream=stream))
     net.close()
@@ -193,8 +221,9 @@ def surrogate_path(args, jt, torch, batch, out, stream, timed, verify):
             "train_s": train_s, "train_steps": steps, "final_batch_loss": float(loss.item()),
             "train_data": "exact classifications at G=16 of 2^20 uniform three-tile "
                           "genotypes and all of S_1,8 (no two-tile genotype)",
-            "kernel": "score (bf16 MFMA) -> order by predicted cost (256-bucket counting "
-                      "sort) -> pipelined classification in that queue order"}
+            "kernel": "predicted cost = size of the deciding run (bf16 MFMA) -> order by "
+                      "predicted cost (256-bucket counting sort) -> pipelined classification "
+                      "in that queue order"}
 
 
 def misclass_report(args, jt, torch):

@@ -443,6 +443,22 @@ int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_
 int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
                     int64_t n, float* scores, void* stream);
 
+/* What jatam_mlp_predict writes per genome (o = the network's four outputs,
+ * p = the softmax of the three class logits o0..o2: UNBOUND, ND, DET):
+ *   SCREEN     p_DET * exp(o3) - 1, as jatam_mlp_score
+ *   COST       exp(o3) - 1: the predicted size of the deciding run, which is
+ *              what the first run costs in placements (plus one); the order
+ *              of a queue by predicted cost
+ *   P_UNBOUND  p_UNBOUND: for a network trained on classifications at G = 16,
+ *              the predicted probability that a run leaves the 16 x 16
+ *              window, i.e. that an item of 16 < G <= 32 needs its own grid */
+enum { JATAM_PREDICT_SCREEN = 0, JATAM_PREDICT_COST = 1, JATAM_PREDICT_P_UNBOUND = 2 };
+
+/* One of the predictions above for each genome (device float [n]); the same
+ * fused pass as jatam_mlp_score.  JATAM_E_INVALID_ARG for an unknown kind. */
+int jatam_mlp_predict(jatam_mlp_t* mlp, int kind, const uint64_t* genomes, const uint8_t* t,
+                      int t_all, int64_t n, float* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Surrogate-screened GA.  A generation draws oversample * n offspring
  * (offspring i exactly as jatam_ga_offspring draws it), scores them with the

@@ -17,7 +17,9 @@ rounded to bf16; h1, h2 and the hidden-layer gradients are rounded to bf16
 (round to nearest even, after rounding to fp32) where the kernels store
 them; every sum is exact here (fp64) where the kernels accumulate in fp32.
 With `bf16=False` no rounding happens at all (pure fp64), which is what the
-finite-difference pins check.
+finite-difference pins check.  `rounding` names the points that round (all
+of ROUNDING by default); a test leaves one out to show that each of them is
+needed to match the kernels.
 """
 from __future__ import annotations
 
@@ -28,6 +30,9 @@ EDGES = 12
 SHAPES = {"w1": (D_IN, H), "b1": (H,), "w2": (H, H), "b2": (H,), "w3": (H, D_OUT),
           "b3": (D_OUT,)}
 ORDER = ("w1", "b1", "w2", "b2", "w3", "b3")
+# where the kernels round to bf16: the weights as used, the two hidden
+# activations and the two hidden-layer gradients
+ROUNDING = ("w", "h1", "h2", "dh2", "dh1")
 
 
 def n_params() -> int:
@@ -70,13 +75,19 @@ def targets(cls: np.ndarray, size: np.ndarray):
     return k.astype(np.int64), np.log1p(np.asarray(size, dtype=np.float64))
 
 
-def forward(p: dict, x: np.ndarray, bf16: bool = True):
-    r = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    w1, w2, w3 = r(p["w1"]), r(p["w2"]), r(p["w3"])
+def _rounder(bf16: bool, rounding, point: str):
+    if bf16 and point in (ROUNDING if rounding is None else rounding):
+        return to_bf16
+    return lambda a: np.asarray(a, dtype=np.float64)
+
+
+def forward(p: dict, x: np.ndarray, bf16: bool = True, rounding=None):
+    rw = _rounder(bf16, rounding, "w")
+    w1, w2, w3 = rw(p["w1"]), rw(p["w2"]), rw(p["w3"])
     a1 = x @ w1 + p["b1"]
-    h1 = r(np.maximum(a1, 0.0))
+    h1 = _rounder(bf16, rounding, "h1")(np.maximum(a1, 0.0))
     a2 = h1 @ w2 + p["b2"]
-    h2 = r(np.maximum(a2, 0.0))
+    h2 = _rounder(bf16, rounding, "h2")(np.maximum(a2, 0.0))
     out = h2 @ w3 + p["b3"]
     return out, {"h1": h1, "h2": h2, "w1": w1, "w2": w2, "w3": w3}
 
@@ -97,27 +108,28 @@ def loss_and_dout(out: np.ndarray, k: np.ndarray, y: np.ndarray):
     return loss, dout
 
 
-def backward(p: dict, x: np.ndarray, cache: dict, dout: np.ndarray, bf16: bool = True):
-    r = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+def backward(p: dict, x: np.ndarray, cache: dict, dout: np.ndarray, bf16: bool = True,
+             rounding=None):
     h1, h2 = cache["h1"], cache["h2"]
     g = {}
     g["w3"] = h2.T @ dout
     g["b3"] = dout.sum(axis=0)
-    dh2 = r((dout @ cache["w3"].T) * (h2 > 0))
+    dh2 = _rounder(bf16, rounding, "dh2")((dout @ cache["w3"].T) * (h2 > 0))
     g["w2"] = h1.T @ dh2
     g["b2"] = dh2.sum(axis=0)
-    dh1 = r((dh2 @ cache["w2"].T) * (h1 > 0))
+    dh1 = _rounder(bf16, rounding, "dh1")((dh2 @ cache["w2"].T) * (h1 > 0))
     g["w1"] = x.T @ dh1
     g["b1"] = dh1.sum(axis=0)
     return g
 
 
-def loss_and_grads(p: dict, genomes, t, cls, size, c: int = 8, bf16: bool = True):
+def loss_and_grads(p: dict, genomes, t, cls, size, c: int = 8, bf16: bool = True,
+                   rounding=None):
     x = encode(genomes, t, c)
     k, y = targets(cls, size)
-    out, cache = forward(p, x, bf16)
+    out, cache = forward(p, x, bf16, rounding)
     loss, dout = loss_and_dout(out, k, y)
-    return loss, backward(p, x, cache, dout, bf16), out
+    return loss, backward(p, x, cache, dout, bf16, rounding), out
 
 
 def adam(p: dict, g: dict, m: dict, v: dict, step: int, lr=1e-3, beta1=0.9, beta2=0.999,

@@ -241,3 +241,51 @@ def true_class(genomes: np.ndarray, t: int, c: int = 8, grid: int = 16,
     if rc != 0:
         raise ValueError(f"oracle rejected arguments (rc={rc})")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Robustness and evolvability (§1.1): the proportion of single mutations that
+# leave the phenotype unchanged, and the number of different phenotypes that
+# single mutations reach.  A single mutation flips one genome bit (the
+# mutation operator of App. B.3 flips bits), so a t-tile genotype with
+# b = log2 c bits per colour has 4*t*b single mutants.  The phenotype of a
+# record is UNBOUND, non-deterministic (ND_SITE or ND_RUNS) or the
+# deterministic shape (size and D4 hash).
+# ---------------------------------------------------------------------------
+def mutants(genomes: np.ndarray, t: int, c: int = 8) -> np.ndarray:
+    """[n, 4*t*b] genomes: column k has bit k flipped (bit 0 the lowest)."""
+    g = np.asarray(genomes, dtype=np.uint64)
+    nbits = 4 * t * (c.bit_length() - 1)
+    flips = np.uint64(1) << np.arange(nbits, dtype=np.uint64)
+    return g[:, None] ^ flips[None, :]
+
+
+def phenotype_keys(rec: np.ndarray) -> np.ndarray:
+    """One uint64 per record: 1 for UNBOUND, 2 for either ND class, and for a
+    DET record 4 + size * 2^32 + hash (never 1 or 2)."""
+    cls = rec["cls"].astype(np.int64)
+    det = (np.uint64(4) + (rec["size"].astype(np.uint64) << np.uint64(32))
+           + rec["hash"].astype(np.uint64))
+    key = np.where(cls == DET, det, np.where(cls == UNBOUND, np.uint64(1), np.uint64(2)))
+    return key.astype(np.uint64)
+
+
+def neighbourhood(genomes: np.ndarray, t: int, c: int = 8, grid: int = 16, runs: int = 20,
+                  seed: int = 1, threads: int = 0):
+    """(robust, evolv) per genotype: robust = how many of its single mutants
+    have its phenotype; evolv = how many distinct phenotypes other than its
+    own its single mutants have.  Every genotype and mutant is classified by
+    the oracle with its default rng_id."""
+    g = np.ascontiguousarray(genomes, dtype=np.uint64)
+    m = mutants(g, t, c)
+    own = phenotype_keys(classify(g, t, c=c, grid=grid, runs=runs, seed=seed,
+                                  threads=threads))
+    mk = phenotype_keys(classify(m.ravel(), t, c=c, grid=grid, runs=runs, seed=seed,
+                                 threads=threads)).reshape(m.shape)
+    robust = np.sum(mk == own[:, None], axis=1).astype(np.int32)
+    evolv = np.zeros(len(g), dtype=np.int32)
+    for i in range(len(g)):
+        others = set(mk[i].tolist())
+        others.discard(int(own[i]))
+        evolv[i] = len(others)
+    return robust, evolv

@@ -930,22 +930,30 @@ int jatam_mlp_train_step(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_
     return rc;
 }
 
-int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
-                    int64_t n, float* scores, void* stream)
+int jatam_mlp_predict(jatam_mlp_t* mlp, int kind, const uint64_t* genomes, const uint8_t* t,
+                      int t_all, int64_t n, float* out, void* stream)
 {
-    if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || scores == nullptr)) ||
-        (t == nullptr && (t_all < 1 || t_all > 3)))
+    if (mlp == nullptr || n < 0 || (n > 0 && (genomes == nullptr || out == nullptr)) ||
+        (t == nullptr && (t_all < 1 || t_all > 3)) ||
+        (kind != JATAM_PREDICT_SCREEN && kind != JATAM_PREDICT_COST &&
+         kind != JATAM_PREDICT_P_UNBOUND))
         return JATAM_E_INVALID_ARG;
     const hipStream_t s = (hipStream_t)stream;
     // one fused pass, in pieces of at most 2^31 samples (no activations kept)
     for (int64_t at = 0; at < n; at += (int64_t)1 << 31) {
         const int64_t k = n - at < ((int64_t)1 << 31) ? n - at : ((int64_t)1 << 31);
         const int rc = jatam::mlp_launch_score(mlp->a, genomes + at, t ? t + at : nullptr, t_all,
-                                               (uint32_t)k, scores + at, s);
+                                               (uint32_t)k, out + at, kind, s);
         if (rc != JATAM_OK)
             return rc;
     }
     return JATAM_OK;
+}
+
+int jatam_mlp_score(jatam_mlp_t* mlp, const uint64_t* genomes, const uint8_t* t, int t_all,
+                    int64_t n, float* scores, void* stream)
+{
+    return jatam_mlp_predict(mlp, JATAM_PREDICT_SCREEN, genomes, t, t_all, n, scores, stream);
 }
 
 }  // extern "C"

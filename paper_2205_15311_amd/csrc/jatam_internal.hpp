@@ -207,7 +207,7 @@ struct MlpArgs {
 size_t mlp_partial_floats(size_t max_batch);
 int mlp_launch_init(const MlpArgs& a, uint64_t seed, hipStream_t s);
 int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
-                     uint32_t n, float* scores, hipStream_t s);
+                     uint32_t n, float* scores, int kind, hipStream_t s);
 int mlp_launch_refresh(const MlpArgs& a, hipStream_t s);
 int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
                        uint32_t n, uint32_t n_pad, const jatam_result_t* labels, float* out4,

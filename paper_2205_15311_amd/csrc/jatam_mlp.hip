@@ -412,11 +412,13 @@ __device__ __forceinline__ bf16x8 onehot_operand(uint64_t g, int t, int bits, ui
     return v;
 }
 
+// kind: JATAM_PREDICT_SCREEN, _COST or _P_UNBOUND (what is written per genome).
 template <int KB1>
 __global__ __launch_bounds__(512) void mlp_score_persistent_kernel(MlpArgs a,
                                                                    const uint64_t* genomes,
                                                                    const uint8_t* tvec, int t_all,
-                                                                   uint32_t n, float* scores)
+                                                                   uint32_t n, float* scores,
+                                                                   int kind)
 {
     __shared__ __attribute__((aligned(16))) uint16_t h1s[kSc2Rows][kSc2Pitch];
     __shared__ __attribute__((aligned(16))) uint16_t h2s[kSc2Rows][kSc2Pitch];
@@ -535,7 +537,10 @@ __global__ __launch_bounds__(512) void mlp_score_persistent_kernel(MlpArgs a,
             if (o == 0 && s0 + (uint32_t)row < n) {
                 const float mx = fmaxf(o0, fmaxf(o1, o2));
                 const float e0 = expf(o0 - mx), e1 = expf(o1 - mx), e2 = expf(o2 - mx);
-                scores[s0 + row] = e2 / (e0 + e1 + e2) * expf(o3) - 1.f;
+                const float inv = 1.f / (e0 + e1 + e2);
+                scores[s0 + row] = kind == JATAM_PREDICT_COST        ? expf(o3) - 1.f
+                                   : kind == JATAM_PREDICT_P_UNBOUND ? e0 * inv
+                                                                     : e2 * inv * expf(o3) - 1.f;
             }
         }
     }
@@ -806,9 +811,9 @@ int mlp_launch_forward(const MlpArgs& a, const uint64_t* genomes, const uint8_t*
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
-// Screening scores of n samples (any n; no padding, no activations kept).
+// Predictions of n samples (any n; no padding, no activations kept).
 int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* tvec, int t_all,
-                     uint32_t n, float* scores, hipStream_t s)
+                     uint32_t n, float* scores, int kind, hipStream_t s)
 {
     if (n == 0)
         return JATAM_OK;
@@ -828,13 +833,13 @@ int mlp_launch_score(const MlpArgs& a, const uint64_t* genomes, const uint8_t* t
     const uint32_t blocks = tiles < (uint32_t)(cus * per_cu) ? tiles : (uint32_t)(cus * per_cu);
     if (kb1 == 1)
         hipLaunchKernelGGL(mlp_score_persistent_kernel<1>, dim3(blocks), dim3(512), 0, s, a,
-                           genomes, tvec, t_all, n, scores);
+                           genomes, tvec, t_all, n, scores, kind);
     else if (kb1 == 2)
         hipLaunchKernelGGL(mlp_score_persistent_kernel<2>, dim3(blocks), dim3(512), 0, s, a,
-                           genomes, tvec, t_all, n, scores);
+                           genomes, tvec, t_all, n, scores, kind);
     else
         hipLaunchKernelGGL(mlp_score_persistent_kernel<3>, dim3(blocks), dim3(512), 0, s, a,
-                           genomes, tvec, t_all, n, scores);
+                           genomes, tvec, t_all, n, scores, kind);
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 

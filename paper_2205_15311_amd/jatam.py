@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         L.jatam_mlp_train_step.restype = i32
         L.jatam_mlp_score.argtypes = [vp, vp, vp, i32, i64, vp, vp]
         L.jatam_mlp_score.restype = i32
+        L.jatam_mlp_predict.argtypes = [vp, i32, vp, vp, i32, i64, vp, vp]
+        L.jatam_mlp_predict.restype = i32
         L.jatam_ga_create.argtypes = [i64, ctypes.POINTER(vp)]
         L.jatam_ga_create.restype = i32
         L.jatam_ga_destroy.argtypes = [vp]
@@ -635,6 +637,7 @@ class Batch:
 
 
 MLP_PARAMS = 91652
+PREDICT_SCREEN, PREDICT_COST, PREDICT_P_UNBOUND = 0, 1, 2   # jatam_mlp_predict kinds
 
 
 class MLP:
@@ -707,6 +710,18 @@ class MLP:
             out = torch.empty(n, dtype=torch.float32, device=genomes.device)
         _check(lib().jatam_mlp_score(self._h, genomes.data_ptr(), tp, ta, n, out.data_ptr(),
                                      _stream_handle(stream)), "jatam_mlp_score")
+        return out
+
+    def predict(self, genomes: torch.Tensor, t, kind: int, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+        """jatam_mlp_predict: PREDICT_SCREEN, PREDICT_COST or PREDICT_P_UNBOUND."""
+        n = genomes.shape[0]
+        tp, ta = self._tiles(t, n)
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=genomes.device)
+        _check(lib().jatam_mlp_predict(self._h, int(kind), genomes.data_ptr(), tp, ta, n,
+                                       out.data_ptr(), _stream_handle(stream)),
+               "jatam_mlp_predict")
         return out
 
     def train_step(self, genomes: torch.Tensor, t, labels: torch.Tensor, lr: float = 1e-3,

@@ -139,3 +139,11 @@ def test_true_class_rejects_bad_arguments(lib):
     assert lib.jatam_truth_create(16, 16, 0, ctypes.byref(h)) == -1
     assert lib.jatam_truth_create(16, 16, 1, None) == -1
     assert lib.jatam_truth_destroy(None) == 0
+
+
+def test_mlp_predict_rejects_bad_arguments(lib):
+    """jatam_mlp_predict validates before touching a network."""
+    buf = ctypes.create_string_buffer(64)
+    for kind in (0, 1, 2, 3, -1):
+        assert lib.jatam_mlp_predict(None, kind, buf, None, 2, 1, buf, None) == -1
+    assert lib.jatam_mlp_score(None, buf, None, 2, 1, buf, None) == -1

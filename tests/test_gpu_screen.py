@@ -64,6 +64,30 @@ def test_scores_match_reference(jt):
     assert np.abs(got - want).max() <= 2e-2 * (np.abs(want).max() + 1)
 
 
+def test_predictions_match_reference(jt):
+    """jatam_mlp_predict's three kinds against the reference network's
+    outputs: the screening score, the predicted size exp(o3) - 1 and the
+    softmax probability of UNBOUND."""
+    p = M.random_params(13)
+    rng = np.random.default_rng(5)
+    g = rng.integers(0, 1 << 36, size=3000, dtype=np.uint64)
+    dg = torch.from_numpy(g.view(np.int64)).cuda()
+    with jt.MLP(1024) as net:
+        net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
+        got = {k: net.predict(dg, 3, k).cpu().numpy().astype(np.float64)
+               for k in (jt.PREDICT_SCREEN, jt.PREDICT_COST, jt.PREDICT_P_UNBOUND)}
+        score = net.score(dg, 3).cpu().numpy()
+    out, _ = M.forward(p, M.encode(g, 3))
+    z = out[:, :3] - out[:, :3].max(axis=1, keepdims=True)
+    prob = np.exp(z) / np.exp(z).sum(axis=1, keepdims=True)
+    want = {jt.PREDICT_SCREEN: prob[:, 2] * np.exp(out[:, 3]) - 1,
+            jt.PREDICT_COST: np.exp(out[:, 3]) - 1,
+            jt.PREDICT_P_UNBOUND: prob[:, 0]}
+    assert np.array_equal(got[jt.PREDICT_SCREEN], score.astype(np.float64))
+    for k, w in want.items():
+        assert np.abs(got[k] - w).max() <= 2e-2 * (np.abs(w).max() + 1), k
+
+
 def test_screened_generation_is_exact_given_scores(jt):
     rng = np.random.default_rng(5)
     n, k = 4096, 4
