@@ -2,14 +2,18 @@
 """Benchmark: genotypes classified per second over the whole of S_{2,8}.
 
 One step = classification of all 2^24 two-tile genotypes (c=8, G=16, R=20,
-seed 1), no input read from HBM, 256 MiB of records written to HBM.  Three
+seed 1), no input read from HBM, 256 MiB of records written to HBM.  Four
 paths are timed on the same stream:
-  plain    16 launches of the plain kernel over 2^20-genotype ranges,
-  graph    one captured pipeline of a 2^20-genotype slice, replayed 16 times,
-  batched  one pipelined call over the whole range (first runs with lane
-           refill, size-ordered repeat runs; the reported value).
+  plain      16 launches of the plain kernel over 2^20-genotype ranges,
+  graph      one captured pipeline of a 2^20-genotype slice, replayed 16 times,
+  surrogate  the trained network's predicted cost of every genotype, the
+             queue ordered by it, the pipelined call in that order (scoring
+             and ordering inside the timed step),
+  batched    one pipelined call over the whole range (first runs with lane
+             refill, size-ordered repeat runs; the reported value).
 The pipeline's launch parameters come from the library's autotuner, run
-(untimed) on the first 2^22 genotypes before timing.
+(untimed) on the same space classified with another seed (2), so the
+timed records are never the ones it tuned on.
 After timing, each path's records are hashed per 2^20 slice and compared
 with the oracle's digests (tests/golden/s28_digests.json), so a rate counts
 only if it is bit-exact.
@@ -17,7 +21,8 @@ only if it is bit-exact.
 Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: the
 benchmark measures one GPU.  The roofline's `traffic` comes from the
 committed counter summary under profiles/ while the kernel sources are the
-ones it was taken on, else null.
+ones it was taken on, else null.  `--paths batched` times the batched path
+alone (for profiles); `--no-autotune` keeps the default launch parameters.
 """
 import argparse
 import hashlib
@@ -29,6 +34,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+TUNE_SEED = 2
 METRIC = "genotypes classified/s, S_2,8 grid16 R20 (bit-exact): plain vs batched+surrogate"
 T, C, GRID, RUNS, SEED = 2, 8, 16, 20, 1
 SLICE = 1 << 20
@@ -388,6 +394,10 @@ def main():
                     help="ga: the surrogate-screened GA report; misclass: the classifier's "
                          "error against the true class over S_2,8, R = 1..20")
     ap.add_argument("--generations", type=int, default=500)
+    ap.add_argument("--paths", default="plain,graph,surrogate,batched",
+                    help="comma-separated subset of the timed paths (batched is always timed)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch parameters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 4 blits and 4 elementwise copies of 256 MiB "
                          "(to scale HBM counters)")
@@ -480,37 +490,62 @@ def main():
         torch.cuda.synchronize()
         return start.elapsed_time(end), ev
 
+    paths = set(args.paths.split(",")) | {"batched"}
+    results = {}
+    bit_exact = True
+
     # plain path: 16 launches per step, each bracketed by events
-    plain_launch_ms = []
+    if "plain" in paths:
+        plain_launch_ms = []
 
-    def plain_timed_step(ev):
-        plain_step(ev)
-        plain_launch_ms.append(ev)
+        def plain_timed_step(ev):
+            plain_step(ev)
+            plain_launch_ms.append(ev)
 
-    plain_total_ms, _ = timed(plain_timed_step, plain_step, make_events=True)
-    plain_ok = verify()
-    launch_ms = [a.elapsed_time(b) for ev in plain_launch_ms for a, b in ev]
-    plain_mean_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
-    plain_value = TOTAL * args.steps / (plain_total_ms / 1e3)
+        plain_total_ms, _ = timed(plain_timed_step, plain_step, make_events=True)
+        plain_ok = verify()
+        bit_exact &= plain_ok
+        launch_ms = [a.elapsed_time(b) for ev in plain_launch_ms for a, b in ev]
+        plain_mean_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+        plain_ops_per_launch = algorithmic_ops(SLICE, gold["steps"] / nslices,
+                                               gold["tally"][3] / nslices,
+                                               gold["det_size"] / nslices)
+        results["plain"] = {
+            "value": TOTAL * args.steps / (plain_total_ms / 1e3),
+            "ms_per_step": plain_total_ms / args.steps, "bit_exact": plain_ok,
+            "mean_launch_ms": plain_mean_launch_s * 1e3,
+            "kernel": "classify_plain_kernel<16,256>, 2^20 genotypes per launch",
+            "roofline_frac": plain_ops_per_launch / plain_mean_launch_s / VALU_PEAK_OPS}
 
-    # launch parameters chosen by the library's autotuner on the timed space
-    # itself (untimed; it rejects any candidate that changes a record)
-    tuning, tune_log = batch.autotune(0, TOTAL, T, C, GRID, RUNS, SEED)
-    # the graph path's workspace is tuned for the slice it replays (a 2^20
-    # slice leaves each of the one-call grid's waves only a few chunks)
-    graph_tuning, _ = graph_batch.autotune(0, SLICE, T, C, GRID, RUNS, SEED)
+    # launch parameters chosen by the library's autotuner (untimed; it
+    # rejects any candidate that changes a record) on the same space
+    # classified with seed 2, so never on the records it then times
+    tuning, tune_log = (batch.get_tuning(GRID), []) if args.no_autotune else \
+        batch.autotune(0, TOTAL, T, C, GRID, RUNS, TUNE_SEED)
 
-    # graph path: one captured 2^20-genotype slice pipeline, replayed 16 times
-    graph_total_ms, _ = timed(graph_step, graph_step)
-    graph_ok = verify()
-    graph_value = TOTAL * args.steps / (graph_total_ms / 1e3)
+    # graph path: one captured 2^20-genotype slice pipeline, replayed 16
+    # times; its workspace is tuned for the slice it replays (a 2^20 slice
+    # leaves each of the one-call grid's waves only a few chunks)
+    if "graph" in paths:
+        graph_tuning = graph_batch.get_tuning(GRID) if args.no_autotune else \
+            graph_batch.autotune(0, SLICE, T, C, GRID, RUNS, TUNE_SEED)[0]
+        graph_total_ms, _ = timed(graph_step, graph_step)
+        graph_ok = verify()
+        bit_exact &= graph_ok
+        results["graph"] = {
+            "value": TOTAL * args.steps / (graph_total_ms / 1e3),
+            "ms_per_step": graph_total_ms / args.steps, "bit_exact": graph_ok,
+            "tuning": graph_tuning,
+            "kernel": "one captured 2^20-genotype slice pipeline, 16 hipGraph replays"}
     graph_batch.close()
 
     # batched + surrogate path: the network (trained untimed, on genotypes
-    # that are not timed) scores every genotype, the queue is ordered by the
-    # predicted cost, and the pipeline takes the range in that order; scoring
-    # and ordering are inside the timed step
-    sur = surrogate_path(args, jt, torch, batch, out, stream, timed, verify)
+    # that are not timed) predicts every genotype's cost, the queue is
+    # ordered by it, and the pipeline takes the range in that order;
+    # prediction and ordering are inside the timed step
+    if "surrogate" in paths:
+        results["surrogate"] = surrogate_path(args, jt, torch, batch, out, stream, timed, verify)
+        bit_exact &= results["surrogate"]["bit_exact"]
 
     # batched path: one call per step, stage events recorded by the library
     batch.set_timing(True)
@@ -518,6 +553,7 @@ def main():
     stages = batch.stage_times()
     batch.set_timing(False)
     batched_ok = verify()
+    bit_exact &= batched_ok
     batched_value = TOTAL * args.steps / (batched_total_ms / 1e3)
 
     ops = stage_ops(gold)
@@ -525,9 +561,9 @@ def main():
     dominant = max(ops, key=lambda k: stage_ms.get(k, 0.0))
     dom_s = stage_ms[dominant] / 1e3
     achieved = ops[dominant] / dom_s
-    plain_ops_per_launch = algorithmic_ops(SLICE, gold["steps"] / nslices,
-                                           gold["tally"][3] / nslices, gold["det_size"] / nslices)
-    bit_exact = plain_ok and batched_ok and graph_ok
+    stage_ms_r = {k: round(v, 4) for k, v in stage_ms.items()}
+    results["batched"] = {"value": batched_value, "ms_per_step": batched_total_ms / args.steps,
+                          "bit_exact": batched_ok, "surrogate": False, "stage_ms": stage_ms_r}
     line = {
         "metric": METRIC,
         "value": batched_value if batched_ok else 0.0,
@@ -546,21 +582,8 @@ def main():
                    "genotypes_per_step": TOTAL, "t": T, "c": C, "grid": GRID, "runs": RUNS,
                    "seed": SEED, "tuning": tuning,
                    "autotune_ms": [round(ms, 4) for _, ms in tune_log]},
-        "bit_exact": bool(bit_exact and sur["bit_exact"]),
-        "paths": {
-            "batched": {"value": batched_value, "ms_per_step": batched_total_ms / args.steps,
-                        "bit_exact": batched_ok, "surrogate": False,
-                        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}},
-            "surrogate": sur,
-            "graph": {"value": graph_value, "ms_per_step": graph_total_ms / args.steps,
-                      "bit_exact": graph_ok, "tuning": graph_tuning,
-                      "kernel": "one captured 2^20-genotype slice pipeline, 16 hipGraph replays"},
-            "plain": {"value": plain_value, "ms_per_step": plain_total_ms / args.steps,
-                      "bit_exact": plain_ok, "mean_launch_ms": plain_mean_launch_s * 1e3,
-                      "kernel": "classify_plain_kernel<16,256>, 2^20 genotypes per launch",
-                      "roofline_frac": plain_ops_per_launch / plain_mean_launch_s
-                      / VALU_PEAK_OPS},
-        },
+        "bit_exact": bool(bit_exact),
+        "paths": results,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": profiled_traffic(dominant), "kernel": dominant,

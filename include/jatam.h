@@ -590,6 +590,102 @@ int jatam_true_class(jatam_truth_t* w, const uint64_t* genotypes, int64_t n, int
 int jatam_true_class_range(jatam_truth_t* w, uint64_t first, int64_t n, int t, int c,
                            int grid_limit, int64_t cap, jatam_result_t* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Robustness and evolvability (§1.1): robustness is the share of a
+ * genotype's single mutations that keep its phenotype, evolvability the
+ * number of different phenotypes its single mutations reach.  A single
+ * mutation flips one genome bit (the bit-flip mutation of App. B.3), so a
+ * genotype of t tiles over c colours has m = 4 t log2(c) single mutants;
+ * mutant k has bit k flipped (bit 0 the lowest).  A phenotype is UNBOUND,
+ * non-deterministic (ND_SITE or ND_RUNS, one phenotype) or a deterministic
+ * shape (size and hash); records of other classes count as
+ * non-deterministic.
+ *   robust  mutants whose phenotype equals the genotype's (0..m)
+ *   evolv   distinct phenotypes among the mutants, the genotype's own
+ *           excluded (0..m)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t robust;
+    int32_t evolv;
+} jatam_neighbourhood_t;
+
+/* The single mutants of n genotypes: mutants[i * m + k] = genotype i with
+ * bit k flipped.  genotypes: device array, or NULL for the range
+ * genotype_i = first + i (which must lie in the space).  mutants: device,
+ * n * m entries.  JATAM_E_INVALID_ARG for bad t, c or range. */
+int jatam_single_mutants(const uint64_t* genotypes, uint64_t first, int64_t n, int t, int c,
+                         uint64_t* mutants, void* stream);
+
+/* Robustness and evolvability of n genotypes from their records (own[i])
+ * and their mutants' records (mutant_records[i * m + k], the records of
+ * jatam_single_mutants' output, classified by any call with the same c,
+ * grid, runs and seed).  All device memory; out: n entries. */
+int jatam_neighbourhood(const jatam_result_t* own, const jatam_result_t* mutant_records,
+                        int64_t n, int t, int c, jatam_neighbourhood_t* out, void* stream);
+
+/* The same for genotypes first .. first + n - 1 of a whole space whose
+ * records are at hand: space[g] is the record of genotype g for every g of
+ * the space (c^(4t) records, m <= 32), so every mutant's record is read,
+ * none classified.  JATAM_E_INVALID_ARG if m > 32 or the range leaves the
+ * space. */
+int jatam_neighbourhood_space(const jatam_result_t* space, uint64_t first, int64_t n, int t,
+                              int c, jatam_neighbourhood_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * The paper's own genetic algorithm (§2.2, §3.1, App. C.1, D.1, D.2):
+ * global roulette wheel selection, single-point crossover and Poisson-
+ * distributed bit-flip mutation, over genomes of L bits (the low L bits of a
+ * uint64_t; bit-string position 0 is bit L-1).
+ *   selection  a dart d = floor(u S / 2^32), S = sum of the fitness, lands on
+ *              the first genome whose running fitness sum exceeds d (App.
+ *              C.1's lookup); uniform when S = 0
+ *   crossover  (crossover = 1) a second parent by a second dart, a point
+ *              p = floor(u L / 2^32): positions 0..p-1 from the second parent
+ *   mutation   k ~ Poisson(lambda) flips, k = the first j with u < T_j,
+ *              T_j = floor(2^32 P(k <= j)) computed on the host in double
+ *              precision (p_0 = exp(-lambda), p_j = p_(j-1) lambda / j), at
+ *              most L; k distinct positions floor(u L / 2^32), a repeat drawn
+ *              again (App. D.1), at most 1024 position draws
+ *   words      offspring i of generation g: Philox4x32-10 keyed by seed, at
+ *              counter (i, g, block, 4 << 28), word q = word q % 4 of block
+ *              q / 4: 0 parent, 1 second parent, 2 point, 3 flip count,
+ *              4.. positions
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;      /* GA seed (Philox key)                              */
+    int32_t length;     /* genome bits L, 1..64                              */
+    int32_t crossover;  /* 0: asexual, 1: single-point crossover             */
+    double lambda;      /* mean flips per offspring, mu L, 0..64             */
+} jatam_roulette_params_t;
+
+/* Device words of the work array of jatam_roulette_offspring for n parents. */
+int64_t jatam_roulette_work_words(int64_t n);
+
+/* n_out offspring of generation `generation` from n parents (device pop[n],
+ * fit[n] with every fitness below 2^16, 1 <= n <= 2^16).  work: device,
+ * jatam_roulette_work_words(n) uint32 (the running fitness sums, the
+ * paper's summation kernel).  out: device, n_out genomes.  The offspring's
+ * fitness is the caller's (Hamming weight, DET size from jatam_classify,
+ * ...).  JATAM_E_INVALID_ARG for bad parameters or sizes. */
+int jatam_roulette_offspring(const uint64_t* pop, const uint32_t* fit, int64_t n,
+                             const jatam_roulette_params_t* p, int32_t generation, int64_t n_out,
+                             uint32_t* work, uint64_t* out, void* stream);
+
+/* The Fujiyama test bed (§4.2): fitness = Hamming weight of the genome;
+ * sims independent simulations at each of rates (1..8) mutation rates
+ * lambdas[k] (host array), each from the all-zero population of pop genomes
+ * (1..1024) and GA seed p->seed + s for simulation s, run in one launch
+ * (one workgroup per simulation, the generation loop in the kernel).
+ * Simulation s at rate k writes, at index s * rates + k of the device arrays
+ * discovery and adaptation, the first generation with a genome of weight >=
+ * target and the first with at least half the population there (generation
+ * 0 is the initial population; -1 if not within cutoff generations); the
+ * simulation stops once both are found or at the cut-off.  final_pop: NULL,
+ * or device [sims * rates * pop]: the population when it stopped. */
+int jatam_fujiyama(const jatam_roulette_params_t* p, const double* lambdas, int32_t rates,
+                   int32_t sims, int32_t pop, int32_t target, int32_t cutoff, int32_t* discovery,
+                   int32_t* adaptation, uint64_t* final_pop, void* stream);
+
 /* Static description of an error code. */
 const char* jatam_strerror(int code);
 

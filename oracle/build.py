@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "jatam_oracle.c"), os.path.join(HERE, "jatam_ga_oracle.c")]
+SRCS = [os.path.join(HERE, "jatam_oracle.c"), os.path.join(HERE, "jatam_ga_oracle.c"),
+        os.path.join(HERE, "jatam_roulette_oracle.c")]
 LIB = os.path.join(HERE, "libjatam_oracle.so")
 
 
@@ -17,7 +18,7 @@ LIB = os.path.join(HERE, "libjatam_oracle.so")
 # (any AVX2-capable x86-64 runs it).
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O3", "-march=x86-64-v3", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-pthread",
-           "-Wall", "-Wextra", "-Werror", "-o", LIB + ".tmp"] + SRCS
+           "-Wall", "-Wextra", "-Werror", "-o", LIB + ".tmp"] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

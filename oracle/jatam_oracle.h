@@ -146,6 +146,37 @@ int jref_ga_step(const uint64_t* pop, const int32_t* fit, int64_t n, int t, int 
                  int runs, uint64_t seed, const jref_ga_params_t* p, int32_t generation,
                  uint64_t* next_pop, int32_t* next_fit, int threads);
 
+/* ---- the paper's GA: roulette, single-point crossover, Poisson bit flips
+ *      (jatam_roulette_oracle.c) ---- */
+typedef struct {
+    uint64_t seed;     /* Philox key of the GA's draws                     */
+    int32_t length;    /* genome bits L, 1..64                             */
+    int32_t crossover; /* 1: single-point crossover with a second parent   */
+    double lambda;     /* mean number of flipped bits per offspring, mu L  */
+} jref_roulette_params_t;
+
+/* App. C.1's lookup: the first index whose running sum of weights reaches
+ * cutoff, or -1. */
+int64_t jref_roulette_lookup(const uint32_t* weights, int64_t n, uint64_t cutoff);
+
+/* thr[j] = floor(2^32 * P(k <= j)) for k Poisson(lambda), j = 0..length
+ * (2^32 once the sum reaches 1). */
+void jref_poisson_thresholds(double lambda, int length, uint64_t* thr);
+
+int jref_roulette_check(const jref_roulette_params_t* p, int64_t n);
+
+/* n_out offspring of generation `generation` from a population of n with
+ * fitness fit (each below 2^16, n <= 2^16). */
+int jref_roulette_offspring(const uint64_t* pop, const uint32_t* fit, int64_t n,
+                            const jref_roulette_params_t* p, int32_t generation, int64_t n_out,
+                            uint64_t* out);
+
+/* One Fujiyama simulation from the all-zero population of n: discovery and
+ * adaptation times of Hamming weight `target` (-1: not within cutoff
+ * generations); final_pop (n entries, or NULL) the population at the end. */
+int jref_fujiyama(const jref_roulette_params_t* p, int64_t n, int32_t target, int32_t cutoff,
+                  int32_t* discovery, int32_t* adaptation, uint64_t* final_pop);
+
 #ifdef __cplusplus
 }
 #endif

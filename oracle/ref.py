@@ -289,3 +289,67 @@ def neighbourhood(genomes: np.ndarray, t: int, c: int = 8, grid: int = 16, runs:
         others.discard(int(own[i]))
         evolv[i] = len(others)
     return robust, evolv
+
+
+# ---------------------------------------------------------------------------
+# The paper's GA (roulette selection, single-point crossover, Poisson bit
+# flips) and its Fujiyama test bed (jatam_roulette_oracle.c).
+# ---------------------------------------------------------------------------
+class RouletteParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("length", ctypes.c_int32),
+                ("crossover", ctypes.c_int32), ("lambda_", ctypes.c_double)]
+
+
+def _roulette_lib():
+    L = lib()
+    if not getattr(L, "_roulette_ready", False):
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.jref_roulette_lookup.argtypes = [vp, i64, ctypes.c_uint64]
+        L.jref_roulette_lookup.restype = i64
+        L.jref_poisson_thresholds.argtypes = [ctypes.c_double, ctypes.c_int, vp]
+        L.jref_poisson_thresholds.restype = None
+        L.jref_roulette_offspring.argtypes = [vp, vp, i64, vp, ctypes.c_int32, i64, vp]
+        L.jref_roulette_offspring.restype = ctypes.c_int
+        L.jref_fujiyama.argtypes = [vp, i64, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.jref_fujiyama.restype = ctypes.c_int
+        L._roulette_ready = True
+    return L
+
+
+def roulette_lookup(weights, cutoff: int) -> int:
+    w = np.ascontiguousarray(weights, dtype=np.uint32)
+    return int(_roulette_lib().jref_roulette_lookup(w.ctypes.data, len(w), cutoff))
+
+
+def poisson_thresholds(lam: float, length: int) -> np.ndarray:
+    thr = np.zeros(length + 1, dtype=np.uint64)
+    _roulette_lib().jref_poisson_thresholds(lam, length, thr.ctypes.data)
+    return thr
+
+
+def roulette_offspring(pop, fit, generation: int, length: int, lam: float, crossover: bool = True,
+                       seed: int = 5, n_out: int | None = None) -> np.ndarray:
+    pop = np.ascontiguousarray(pop, dtype=np.uint64)
+    fit = np.ascontiguousarray(fit, dtype=np.uint32)
+    n_out = len(pop) if n_out is None else n_out
+    out = np.zeros(n_out, dtype=np.uint64)
+    p = RouletteParams(seed, length, 1 if crossover else 0, lam)
+    rc = _roulette_lib().jref_roulette_offspring(pop.ctypes.data, fit.ctypes.data, len(pop),
+                                                 ctypes.byref(p), generation, n_out,
+                                                 out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def fujiyama(n: int, length: int, lam: float, target: int, cutoff: int, seed: int = 5,
+             crossover: bool = True):
+    """(discovery, adaptation, final population) of one simulation."""
+    p = RouletteParams(seed, length, 1 if crossover else 0, lam)
+    d, a = ctypes.c_int32(0), ctypes.c_int32(0)
+    final = np.zeros(n, dtype=np.uint64)
+    rc = _roulette_lib().jref_fujiyama(ctypes.byref(p), n, target, cutoff, ctypes.byref(d),
+                                       ctypes.byref(a), final.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return int(d.value), int(a.value), final

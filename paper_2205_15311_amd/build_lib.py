@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjatam.so")
 SOURCES = ["jatam_plain.hip", "jatam_batched.hip", "jatam_ga.hip", "jatam_mlp.hip",
            "jatam_select.hip", "jatam_tally.hip", "jatam_static.hip", "jatam_truth.hip",
-           "jatam_api.cpp"]
+           "jatam_neighbourhood.hip", "jatam_roulette.hip", "jatam_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

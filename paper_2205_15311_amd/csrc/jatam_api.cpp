@@ -68,7 +68,7 @@ std::vector<int> wave_choices(int occ)
 
 extern "C" {
 
-int jatam_abi_version(void) { return 5; }
+int jatam_abi_version(void) { return 6; }
 
 const char* jatam_strerror(int code)
 {

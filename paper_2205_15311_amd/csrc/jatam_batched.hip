@@ -287,6 +287,46 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     int ev = kEvNone;
 
     for (;;) {
+        // -- lanes whose first run is over: records, hashes, staging ----------
+        const bool finish = busy && run_over(ev, st, gd.grid);
+        if (__ballot(finish) != 0) {
+            bool done = false, candidate = false, det = false;
+            int cls = 0;
+            jatam_result_t rec{0, 0, 0u, 0};
+            if (finish) {
+                done = true;
+                if (ev == kEvCorrupt) {
+                    rec = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
+                    cls = JATAM_INVALID;
+                } else if (ev != kEvNone) {
+                    cls = ev == kEvUnbound ? JATAM_UNBOUND : JATAM_ND_SITE;
+                    rec = jatam_result_t{cls, st.size, 0u, st.steps};
+                } else if (!st.choice || a.runs == 1) {
+                    // no random word was drawn: every run would be this run
+                    cls = JATAM_DET;
+                    det = true;
+                    rec = jatam_result_t{JATAM_DET, st.size, 0u, st.steps};
+                } else {
+                    done = false;
+                    candidate = true;
+                }
+            }
+            if (__ballot(det) != 0)
+                rec.hash = det_hash(g, small0, small1, cache, det, st.size, gd.grid);
+            if (finish) {
+                if (done)
+                    out[idx] = rec;
+                busy = false;
+            }
+            tally.add(done, cls);
+            const uint64_t cm = __ballot(candidate);
+            if (candidate) {
+                const uint32_t pos = staged + (uint32_t)__popcll(cm & lanes_below());
+                seg_idx[pos] = idx;
+                seg_size[pos] = (uint16_t)st.size;
+            }
+            staged += (uint32_t)__popcll(cm);
+        }
         // -- refill idle lanes once enough of them wait -----------------------
         const uint64_t idle = __ballot(!busy);
         const uint32_t nidle = (uint32_t)__popcll(idle);
@@ -395,51 +435,24 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 break;
             continue;
         }
-        // -- one step of every busy lane ---------------------------------------
-        const bool stepping = busy && !run_over(ev, st, gd.grid);
-        prefetch_draws(dc, stepping, st, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
-                       (uint32_t)(gd.rng_id >> 32));
-        if (stepping)
-            ev = run_step(m, g, st, dc, gd.grid, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
-                          (uint32_t)(gd.rng_id >> 32));
-        // -- lanes whose first run is over ----------------------------------
-        const bool finish = busy && run_over(ev, st, gd.grid);
-        bool done = false, candidate = false, det = false;
-        int cls = 0;
-        jatam_result_t rec{0, 0, 0u, 0};
-        if (finish) {
-            done = true;
-            if (ev == kEvCorrupt) {
-                rec = jatam_result_t{JATAM_INVALID, 0, 0u, 0};
-                cls = JATAM_INVALID;
-            } else if (ev != kEvNone) {
-                cls = ev == kEvUnbound ? JATAM_UNBOUND : JATAM_ND_SITE;
-                rec = jatam_result_t{cls, st.size, 0u, st.steps};
-            } else if (!st.choice || a.runs == 1) {
-                // no random word was drawn: every run would be this run
-                cls = JATAM_DET;
-                det = true;
-                rec = jatam_result_t{JATAM_DET, st.size, 0u, st.steps};
-            } else {
-                done = false;
-                candidate = true;
-            }
+        // -- steps until enough lanes wait for a refill (every lane, once no
+        // chunk is left), at least one step: finished lanes keep their run's
+        // state until the finish pass above takes them, so records, hashes
+        // and staging are done once per refill rather than at every step ---
+        const uint32_t enough = queued == 0 && starved ? 65u : (uint32_t)a.refill;
+        for (;;) {
+            const bool stepping = busy && !run_over(ev, st, gd.grid);
+            if (__ballot(stepping) == 0)
+                break;
+            prefetch_draws(dc, stepping, st, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
+                           (uint32_t)(gd.rng_id >> 32));
+            if (stepping)
+                ev = run_step(m, g, st, dc, gd.grid, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
+                              (uint32_t)(gd.rng_id >> 32));
+            const uint64_t waiting = __ballot(!busy || run_over(ev, st, gd.grid));
+            if ((uint32_t)__popcll(waiting) >= enough)
+                break;
         }
-        if (__ballot(det) != 0)
-            rec.hash = det_hash(g, small0, small1, cache, det, st.size, gd.grid);
-        if (finish) {
-            if (done)
-                out[idx] = rec;
-            busy = false;
-        }
-        tally.add(done, cls);
-        const uint64_t cm = __ballot(candidate);
-        if (candidate) {
-            const uint32_t pos = staged + (uint32_t)__popcll(cm & lanes_below());
-            seg_idx[pos] = idx;
-            seg_size[pos] = (uint16_t)st.size;
-        }
-        staged += (uint32_t)__popcll(cm);
     }
     if (lane_id() == 0)
         a.ws.seg_count[klass][wave] = staged;

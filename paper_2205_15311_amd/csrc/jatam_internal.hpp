@@ -128,6 +128,47 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
                        DeviceWorkspace* ws);
 // Validates and digests the arguments shared by every classification call.
 int make_params(int t, int c, int grid, int runs, uint64_t seed, Params* p);
+
+// The paper's GA: roulette, single-point crossover, Poisson bit flips
+// (jatam_roulette.hip).
+constexpr int kPoissonMax = 64;     // flip-count thresholds T_0 .. T_L, L <= 64
+constexpr int kFujiMaxPop = 1024;   // one lane per genome, one workgroup per simulation
+constexpr int kFujiMaxRates = 8;    // mutation rates per Fujiyama launch
+
+struct PoissonTable {
+    uint32_t tm1[kPoissonMax + 1];  // T_j - 1 where T_j >= 1
+    uint64_t zero;                  // bit j: T_j == 0
+};
+
+struct RouletteArgs {
+    uint32_t key0, key1;            // Philox key = GA seed
+    int length;                     // genome bits L
+    int crossover;                  // 1: single-point crossover with a second parent
+    PoissonTable poisson;
+};
+
+struct FujiyamaArgs {
+    RouletteArgs r;                 // length and crossover (keys set per simulation)
+    uint64_t seed;                  // simulation s uses GA seed seed + s
+    int rates, sims, pop, target, cutoff;
+    int32_t* discovery;             // [sims * rates], index s * rates + k
+    int32_t* adaptation;
+    uint64_t* final_pop;            // nullptr, or [sims * rates * pop]
+    PoissonTable poisson[kFujiMaxRates];
+};
+
+int launch_roulette_offspring(const uint64_t* pop, const uint32_t* fit, uint32_t n,
+                              const RouletteArgs& r, int32_t generation, uint32_t n_out,
+                              uint32_t* sums, uint64_t* out, hipStream_t s);
+int launch_fujiyama(const FujiyamaArgs& f, hipStream_t s);
+
+// Robustness and evolvability (jatam_neighbourhood.hip).
+int launch_mutants(const uint64_t* genomes, uint64_t first, int64_t n, int nbits, uint64_t* out,
+                   hipStream_t s);
+int launch_neighbourhood(const jatam_result_t* own, const jatam_result_t* mut, int64_t n,
+                         int nbits, jatam_neighbourhood_t* out, hipStream_t s);
+int launch_neighbourhood_space(const jatam_result_t* space, uint64_t first, int64_t n, int nbits,
+                               jatam_neighbourhood_t* out, hipStream_t s);
 // Arguments of a pipelined call over a workspace (range mode, no order).
 BatchArgs batch_args_for(const Params& p, int64_t n, jatam_result_t* out, uint64_t* tally,
                          const DeviceWorkspace& ws, const uint32_t small_hash[2]);

@@ -122,6 +122,19 @@ def lib() -> ctypes.CDLL:
         L.jatam_classify_static.restype = i32
         L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
+        L.jatam_single_mutants.argtypes = [vp, u64, i64, i32, i32, vp, vp]
+        L.jatam_single_mutants.restype = i32
+        L.jatam_neighbourhood.argtypes = [vp, vp, i64, i32, i32, vp, vp]
+        L.jatam_neighbourhood.restype = i32
+        L.jatam_neighbourhood_space.argtypes = [vp, u64, i64, i32, i32, vp, vp]
+        L.jatam_neighbourhood_space.restype = i32
+        L.jatam_roulette_work_words.argtypes = [i64]
+        L.jatam_roulette_work_words.restype = i64
+        L.jatam_roulette_offspring.argtypes = [vp, vp, i64, vp, ctypes.c_int32, i64, vp, vp, vp]
+        L.jatam_roulette_offspring.restype = i32
+        L.jatam_fujiyama.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        L.jatam_fujiyama.restype = i32
         L.jatam_shape_histogram.restype = i32
         L.jatam_batch_classify_range_ordered.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64,
                                                          vp, vp, vp, vp]
@@ -320,6 +333,119 @@ def shape_histogram(records: torch.Tensor, table: torch.Tensor | None = None,
                                      _stream_handle(stream))
     _check(rc, "jatam_shape_histogram")
     return table
+
+
+def _records_arg(rec: torch.Tensor, name: str) -> None:
+    if rec.dtype != torch.int32 or rec.dim() != 2 or rec.shape[1] != 4 or not rec.is_cuda \
+            or not rec.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device int32 tensor (n, 4)")
+
+
+def mutant_count(t: int, c: int = 8) -> int:
+    """Single mutants per genotype: one per genome bit."""
+    return 4 * t * (c.bit_length() - 1)
+
+
+def single_mutants(genotypes: torch.Tensor | None, t: int, c: int = 8, first: int = 0,
+                   n: int | None = None, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """jatam_single_mutants: (n, m) int64 device tensor, entry [i, k] =
+    genotype i with bit k flipped; genotypes None means the range first + i."""
+    if genotypes is not None:
+        n = genotypes.shape[0]
+        dev = genotypes.device
+    else:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    m = mutant_count(t, c)
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.int64, device=dev)
+    _check(lib().jatam_single_mutants(genotypes.data_ptr() if genotypes is not None else None,
+                                      first, n, t, c, out.data_ptr(), _stream_handle(stream)),
+           "jatam_single_mutants")
+    return out
+
+
+def neighbourhood(own: torch.Tensor, mutant_records: torch.Tensor, t: int, c: int = 8,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """jatam_neighbourhood: (n, 2) int32 [robust, evolv] from the genotypes'
+    records and their mutants' records ((n * m, 4), mutant k of genotype i
+    at row i * m + k)."""
+    _records_arg(own, "own")
+    _records_arg(mutant_records, "mutant_records")
+    n = own.shape[0]
+    if mutant_records.shape[0] != n * mutant_count(t, c):
+        raise ValueError("mutant_records must hold n * m records")
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device=own.device)
+    _check(lib().jatam_neighbourhood(own.data_ptr(), mutant_records.data_ptr(), n, t, c,
+                                     out.data_ptr(), _stream_handle(stream)),
+           "jatam_neighbourhood")
+    return out
+
+
+def neighbourhood_space(space: torch.Tensor, t: int, c: int = 8, first: int = 0,
+                        n: int | None = None, out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    """jatam_neighbourhood_space: (n, 2) int32 [robust, evolv] of genotypes
+    first .. first + n - 1, space holding the records of the whole space."""
+    _records_arg(space, "space")
+    if space.shape[0] != c ** (4 * t):
+        raise ValueError("space must hold the records of all c^(4t) genotypes")
+    n = space.shape[0] - first if n is None else n
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device=space.device)
+    _check(lib().jatam_neighbourhood_space(space.data_ptr(), first, n, t, c, out.data_ptr(),
+                                           _stream_handle(stream)),
+           "jatam_neighbourhood_space")
+    return out
+
+
+class RouletteParams(ctypes.Structure):
+    """jatam_roulette_params_t."""
+    _fields_ = [("seed", ctypes.c_uint64), ("length", ctypes.c_int32),
+                ("crossover", ctypes.c_int32), ("lambda_", ctypes.c_double)]
+
+
+def roulette_offspring(pop: torch.Tensor, fit: torch.Tensor, generation: int, length: int,
+                       lam: float, crossover: bool = True, seed: int = 5,
+                       n_out: int | None = None, out: torch.Tensor | None = None,
+                       work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """jatam_roulette_offspring: pop int64 (n,), fit int32/uint32 (n,) device
+    tensors; returns n_out offspring (int64)."""
+    n = pop.shape[0]
+    n_out = n if n_out is None else n_out
+    if pop.dtype != torch.int64 or fit.dtype not in (torch.int32, torch.uint32) \
+            or fit.shape[0] != n or not pop.is_contiguous() or not fit.is_contiguous():
+        raise ValueError("pop must be int64 (n,), fit int32 (n,), both contiguous")
+    if out is None:
+        out = torch.empty(n_out, dtype=torch.int64, device=pop.device)
+    if work is None:
+        work = torch.empty(int(lib().jatam_roulette_work_words(n)), dtype=torch.int32,
+                           device=pop.device)
+    p = RouletteParams(seed, length, 1 if crossover else 0, lam)
+    _check(lib().jatam_roulette_offspring(pop.data_ptr(), fit.data_ptr(), n, ctypes.byref(p),
+                                          generation, n_out, work.data_ptr(), out.data_ptr(),
+                                          _stream_handle(stream)), "jatam_roulette_offspring")
+    return out
+
+
+def fujiyama(lambdas, sims: int, pop: int, length: int, target: int, cutoff: int,
+             seed: int = 5, crossover: bool = True, final_pop: bool = False, device="cuda",
+             stream=None):
+    """jatam_fujiyama: (discovery, adaptation) int32 device tensors (sims,
+    rates), and the final populations (sims, rates, pop) if asked."""
+    lam = (ctypes.c_double * len(lambdas))(*[float(x) for x in lambdas])
+    rates = len(lambdas)
+    disc = torch.empty((sims, rates), dtype=torch.int32, device=device)
+    adap = torch.empty((sims, rates), dtype=torch.int32, device=device)
+    fin = torch.empty((sims, rates, pop), dtype=torch.int64, device=device) if final_pop \
+        else None
+    p = RouletteParams(seed, length, 1 if crossover else 0, 0.0)
+    _check(lib().jatam_fujiyama(ctypes.byref(p), lam, rates, sims, pop, target, cutoff,
+                                disc.data_ptr(), adap.data_ptr(),
+                                fin.data_ptr() if fin is not None else None,
+                                _stream_handle(stream)), "jatam_fujiyama")
+    return (disc, adap, fin) if final_pop else (disc, adap)
 
 
 def shape_table_to_numpy(table: torch.Tensor):

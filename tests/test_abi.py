@@ -147,3 +147,47 @@ def test_mlp_predict_rejects_bad_arguments(lib):
     for kind in (0, 1, 2, 3, -1):
         assert lib.jatam_mlp_predict(None, kind, buf, None, 2, 1, buf, None) == -1
     assert lib.jatam_mlp_score(None, buf, None, 2, 1, buf, None) == -1
+
+
+def test_neighbourhood_rejects_bad_arguments(lib):
+    buf = ctypes.create_string_buffer(64)
+    # bad t or c; a range beyond the space; a space too large to gather from
+    assert lib.jatam_single_mutants(None, 0, 1, 0, 8, buf, None) == -1
+    assert lib.jatam_single_mutants(None, 0, 1, 2, 3, buf, None) == -1
+    assert lib.jatam_single_mutants(None, (1 << 24) - 1, 2, 2, 8, buf, None) == -1
+    assert lib.jatam_single_mutants(None, 0, 1, 2, 8, None, None) == -1
+    assert lib.jatam_neighbourhood(buf, None, 1, 2, 8, buf, None) == -1
+    assert lib.jatam_neighbourhood_space(buf, 0, 1, 3, 8, buf, None) == -1
+    assert lib.jatam_neighbourhood_space(buf, (1 << 24) - 1, 2, 2, 8, buf, None) == -1
+    # empty calls launch nothing
+    assert lib.jatam_single_mutants(None, 0, 0, 2, 8, None, None) == 0
+    assert lib.jatam_neighbourhood(None, None, 0, 2, 8, None, None) == 0
+    assert lib.jatam_neighbourhood_space(None, 0, 0, 2, 8, None, None) == 0
+
+
+def test_roulette_rejects_bad_arguments(lib):
+    from paper_2205_15311_amd import jatam
+    buf = ctypes.create_string_buffer(64)
+    good = jatam.RouletteParams(5, 32, 1, 0.5)
+    lam = (ctypes.c_double * 2)(0.5, 1.0)
+    for bad in (jatam.RouletteParams(5, 0, 1, 0.5), jatam.RouletteParams(5, 65, 1, 0.5),
+                jatam.RouletteParams(5, 32, 2, 0.5), jatam.RouletteParams(5, 32, 1, -1.0),
+                jatam.RouletteParams(5, 32, 1, 65.0)):
+        assert lib.jatam_roulette_offspring(buf, buf, 4, ctypes.byref(bad), 0, 4, buf, buf,
+                                            None) == -1
+        assert lib.jatam_fujiyama(ctypes.byref(bad), lam, 2, 1, 64, 10, 100, buf, buf, None,
+                                  None) == -1
+    # population size, missing buffers, rate and population limits, target
+    assert lib.jatam_roulette_offspring(buf, buf, 0, ctypes.byref(good), 0, 4, buf, buf,
+                                        None) == -1
+    assert lib.jatam_roulette_offspring(buf, buf, 65537, ctypes.byref(good), 0, 4, buf, buf,
+                                        None) == -1
+    assert lib.jatam_roulette_offspring(buf, buf, 4, ctypes.byref(good), 0, 4, None, buf,
+                                        None) == -1
+    lam9 = (ctypes.c_double * 9)(*([0.5] * 9))
+    assert lib.jatam_fujiyama(ctypes.byref(good), lam9, 9, 1, 64, 10, 100, buf, buf, None,
+                              None) == -1
+    assert lib.jatam_fujiyama(ctypes.byref(good), lam, 2, 1, 1025, 10, 100, buf, buf, None,
+                              None) == -1
+    assert lib.jatam_fujiyama(ctypes.byref(good), lam, 2, 1, 64, 33, 100, buf, buf, None,
+                              None) == -1

@@ -1,13 +1,16 @@
 """The surrogate MLP on the GPU against the reference network (oracle/
-mlp_ref.py, fp64 with the same bf16 rounding points).
+mlp_ref.py, fp64 with the kernels' bf16 rounding points).
 
-Tolerances: every product accumulates in fp32 on the GPU and exactly in the
-reference, and the four bf16 roundings (h1, h2, dh2, dh1) can land on
-different sides of a rounding boundary when the fp32 and fp64 sums differ by
-a few fp32 ulps (a fraction ~1e-4 of the elements, each then 1 bf16 ulp =
-2^-8 off).  The forward output is therefore compared to 1e-2 of its scale,
-each gradient tensor to 2% in relative Frobenius norm, and Adam steps (which
-normalise the gradient) elementwise where the gradient is well determined.
+Tolerances, from measured errors: over six seeded networks and batches of
+4096, the forward output differed from the reference by at most 3.3e-4 of
+its scale (2.4e-5 relative, Frobenius), the screening score by 2.3e-4 of its
+scale, each gradient tensor by at most 5.6e-6 relative (1.9e-5 of its
+largest element) and each Adam step by at most 2.6e-4 of the learning rate.
+The tests allow about four times that.  Those residues come from fp32 sums
+in another order than the reference's exact ones; leaving out any one of the
+five bf16 rounding points in the reference instead costs 1.5e-4 to 6e-3 (a
+gradient or the output), which the tolerances reject
+(test_each_rounding_point_is_needed).
 """
 import numpy as np
 import pytest
@@ -50,35 +53,73 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
-def test_forward_matches_reference(jt):
-    p = M.random_params(3)
-    g, t, _, _ = sample(1000, 1)
+FWD_MAX, FWD_REL = 1.5e-3, 1e-4          # of the output's scale; relative Frobenius
+GRAD_REL, GRAD_MAX = 3e-5, 1e-4          # per tensor: relative Frobenius; of its largest element
+ADAM_ABS = 1e-3                          # of the learning rate, every element
+
+
+def gpu_forward_and_grads(jt, p, g, t, cls, size):
     with jt.MLP(4096) as net:
         net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
-        dg, dt = to_dev(g, t)
+        dg, dt, lab = to_dev(g, t, cls, size)
         out = net.forward(dg, dt).cpu().numpy().astype(np.float64)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        net.train_step(dg, dt, lab, lr=0.0, loss=loss)
+        _, grads = net.get_params(grads=True)
+        grads = M.unflatten(grads.cpu().numpy().astype(np.float64))
+        return out, grads, float(loss.item())
+
+
+def forward_ok(out, want):
+    scale = np.abs(want).max()
+    return np.abs(out - want).max() <= FWD_MAX * scale and rel(out, want) <= FWD_REL
+
+
+def grads_ok(grads, want):
+    return all(rel(grads[k], want[k]) <= GRAD_REL
+               and np.abs(grads[k] - want[k]).max() <= GRAD_MAX * np.abs(want[k]).max()
+               for k in M.ORDER)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_forward_matches_reference(jt, seed):
+    p = M.random_params(seed)
+    g, t, cls, size = sample(1000 + 500 * seed, seed)
+    out, _, _ = gpu_forward_and_grads(jt, p, g, t, cls, size)
     want, _ = M.forward(p, M.encode(g, t))
     scale = np.abs(want).max()
-    assert np.abs(out - want).max() <= 1e-2 * scale, np.abs(out - want).max() / scale
-    assert rel(out, want) < 2e-3
+    assert forward_ok(out, want), (np.abs(out - want).max() / scale, rel(out, want))
 
 
 @pytest.mark.parametrize("n", [32, 1000, 4096])
 def test_gradients_match_reference(jt, n):
     p = M.random_params(5, scale=0.7)
     g, t, cls, size = sample(n, n)
-    with jt.MLP(4096) as net:
-        net.set_params(torch.from_numpy(M.flatten(p).astype(np.float32)).cuda())
-        dg, dt, lab = to_dev(g, t, cls, size)
-        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-        net.train_step(dg, dt, lab, lr=0.0, loss=loss)
-        _, grads = net.get_params(grads=True)
-        grads = M.unflatten(grads.cpu().numpy().astype(np.float64))
-        got_loss = float(loss.item())
+    _, grads, got_loss = gpu_forward_and_grads(jt, p, g, t, cls, size)
     want_loss, want, _ = M.loss_and_grads(p, g, t, cls, size)
-    assert abs(got_loss - want_loss) <= 1e-3 * abs(want_loss)
+    assert abs(got_loss - want_loss) <= 1e-6 * abs(want_loss)
     for k in M.ORDER:
-        assert rel(grads[k], want[k]) < 2e-2, (k, rel(grads[k], want[k]))
+        assert rel(grads[k], want[k]) <= GRAD_REL, (k, rel(grads[k], want[k]))
+        assert np.abs(grads[k] - want[k]).max() <= GRAD_MAX * np.abs(want[k]).max(), k
+
+
+def test_each_rounding_point_is_needed(jt):
+    """With every bf16 rounding point the reference matches the kernels to
+    the tolerances above; with any one of them left out it does not (the
+    weights and the two activations show in the output, the two hidden
+    gradients in the weight gradients)."""
+    p = M.random_params(21, scale=0.8)
+    g, t, cls, size = sample(4096, 21)
+    out, grads, _ = gpu_forward_and_grads(jt, p, g, t, cls, size)
+    x = M.encode(g, t)
+    want, _ = M.forward(p, x)
+    _, want_g, _ = M.loss_and_grads(p, g, t, cls, size)
+    assert forward_ok(out, want) and grads_ok(grads, want_g)
+    for point in M.ROUNDING:
+        keep = tuple(q for q in M.ROUNDING if q != point)
+        w, _ = M.forward(p, x, rounding=keep)
+        _, wg, _ = M.loss_and_grads(p, g, t, cls, size, rounding=keep)
+        assert not (forward_ok(out, w) and grads_ok(grads, wg)), point
 
 
 def test_adam_step_matches_reference(jt):
@@ -97,8 +138,8 @@ def test_adam_step_matches_reference(jt):
     for k in M.ORDER:
         step_got, step_want = p[k] - after[k], p[k] - want[k]
         assert np.all(np.abs(step_got) <= lr * (1 + 1e-3) + 1e-7)
-        sure = np.abs(want_g[k]) > 0.05 * np.abs(want_g[k]).max()
-        assert np.allclose(step_got[sure], step_want[sure], rtol=0.05, atol=2e-6), k
+        assert np.abs(step_got - step_want).max() <= ADAM_ABS * lr, \
+            (k, np.abs(step_got - step_want).max() / lr)
 
 
 def test_training_reduces_loss_on_s28_labels(jt):

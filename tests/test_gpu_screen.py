@@ -61,7 +61,7 @@ def test_scores_match_reference(jt):
     z = out[:, :3] - out[:, :3].max(axis=1, keepdims=True)
     pdet = np.exp(z[:, 2]) / np.exp(z).sum(axis=1)
     want = pdet * np.exp(out[:, 3]) - 1
-    assert np.abs(got - want).max() <= 2e-2 * (np.abs(want).max() + 1)
+    assert np.abs(got - want).max() <= 1e-3 * (np.abs(want).max() + 1)
 
 
 def test_predictions_match_reference(jt):
@@ -85,7 +85,7 @@ def test_predictions_match_reference(jt):
             jt.PREDICT_P_UNBOUND: prob[:, 0]}
     assert np.array_equal(got[jt.PREDICT_SCREEN], score.astype(np.float64))
     for k, w in want.items():
-        assert np.abs(got[k] - w).max() <= 2e-2 * (np.abs(w).max() + 1), k
+        assert np.abs(got[k] - w).max() <= 2e-3 * (np.abs(w).max() + 1), k
 
 
 def test_screened_generation_is_exact_given_scores(jt):
