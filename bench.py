@@ -381,6 +381,121 @@ def ga_report(args, jt, torch):
     print(json.dumps(line), flush=True)
 
 
+def maps_report(args, jt, torch):
+    """Robustness and evolvability (section 1.1) of every genotype of S_{2,8}
+    (G=16, R=20, seed 1; the space classified once, every single mutant's
+    record gathered from it) and of a uniform sample of 2^20 three-tile
+    genotypes at G=32 (their 36 single mutants each classified by the
+    pipelined path).  Prints one JSON line."""
+    import numpy as np
+    from tests import inputs
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def timed_call(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b) / 1e3
+
+    def summarise(own, nb, m):
+        cls = own[:, 0]
+        group = np.where(cls == 0, "unbound", np.where(cls == 3, "det", "nd"))
+        out = {}
+        for gname in ("det", "nd", "unbound"):
+            sel = group == gname
+            if not sel.any():
+                continue
+            r, e = nb[sel, 0], nb[sel, 1]
+            out[gname] = {"genotypes": int(sel.sum()), "mean_robustness": float(r.mean() / m),
+                          "mean_evolvability": float(e.mean()),
+                          "evolvability_histogram": np.bincount(e, minlength=4).tolist()[:12]}
+        return out
+
+    res = {}
+    with jt.Batch(TOTAL) as b:
+        space = torch.empty((TOTAL, 4), dtype=torch.int32, device=dev)
+        _, t_cls = timed_call(lambda: b.classify_range(0, TOTAL, T, C, GRID, RUNS, SEED,
+                                                       out=space))
+        nb, t_nb = timed_call(lambda: jt.neighbourhood_space(space, T))
+        m = jt.mutant_count(T)
+        res["s28"] = {"genotypes": TOTAL, "mutants_per_genotype": m,
+                      "classify_s": t_cls, "neighbourhood_s": t_nb,
+                      "genotypes_per_s": TOTAL / (t_cls + t_nb),
+                      "by_phenotype": summarise(space.cpu().numpy(), nb.cpu().numpy(), m)}
+        del space, nb
+    n3, grid3 = 1 << 20, 32
+    g3 = torch.from_numpy(inputs.three_tile_sample(n3, key=13).view(np.int64)).to(dev)
+    m3 = jt.mutant_count(3)
+    with jt.Batch(n3 * m3) as b:
+        def three():
+            own = b.classify(g3, 3, C, grid3, RUNS, SEED)
+            mut = jt.single_mutants(g3, 3)
+            mrec = b.classify(mut.reshape(-1), 3, C, grid3, RUNS, SEED)
+            return own, jt.neighbourhood(own, mrec, 3)
+        (own3, nb3), t3 = timed_call(three)
+        res["s38_sample"] = {"genotypes": n3, "grid": grid3, "mutants_per_genotype": m3,
+                             "seconds": t3, "genotypes_per_s": n3 / t3,
+                             "classifications_per_s": n3 * (m3 + 1) / t3,
+                             "by_phenotype": summarise(own3.cpu().numpy(), nb3.cpu().numpy(),
+                                                       m3)}
+    print(json.dumps({"metric": "robustness and evolvability of S_2,8 (whole space) and of "
+                                "2^20 three-tile genotypes at G=32",
+                      "n_gpus": 1, "data": "exhaustive S_2,8; uniform three-tile sample "
+                                           "(numpy Philox key 13)", "results": res}),
+          flush=True)
+
+
+def fujiyama_report(args, jt, torch):
+    """The paper's GA on the Fujiyama landscape (section 4.2): fitness = Hamming
+    weight of a 32-bit genome, population 512 from all zeros, roulette
+    selection, single-point crossover, Poisson bit flips; 100 simulations
+    per mutation rate mu L, cut-off 20000 generations; median discovery and
+    adaptation times of weight 25, with bootstrap intervals.  Prints one
+    JSON line."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    rates = [0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 4.0, 8.0]
+    sims, pop, L, target, cutoff = 100, 512, 32, 25, 20000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    disc, adap = jt.fujiyama(rates, sims, pop, L, target, cutoff, seed=1000, device=dev)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    disc, adap = disc.cpu().numpy(), adap.cpu().numpy()
+    rng = np.random.default_rng(0)
+
+    def median_ci(x):
+        x = np.where(x < 0, cutoff + 1, x).astype(np.float64)   # not reached: past the cut-off
+        boots = np.median(rng.choice(x, size=(10_000, len(x))), axis=1)
+        return {"median": float(np.median(x)), "ci95": [float(np.percentile(boots, 2.5)),
+                                                        float(np.percentile(boots, 97.5))],
+                "not_reached": int(np.sum(x > cutoff))}
+
+    per_rate = {str(r): {"discovery": median_ci(disc[:, k]), "adaptation": median_ci(adap[:, k])}
+                for k, r in enumerate(rates)}
+    gens = np.where(np.maximum(disc, adap) < 0, cutoff, np.maximum(disc, adap)).sum()
+    line = {"metric": "Fujiyama test bed of the paper's GA: population 512, L=32, target "
+                      "weight 25, 100 simulations per rate, cut-off 20000",
+            "n_gpus": 1, "seconds": secs, "simulations": sims * len(rates),
+            "generations_evolved": int(gens), "genomes_per_s": float(gens) * pop / secs,
+            "per_rate": per_rate}
+    if not args.no_cpu_baseline:
+        from oracle import ref
+        t1 = time.perf_counter()
+        d, a, _ = ref.fujiyama(pop, L, 0.5, target, 2000, seed=1000)
+        dt = time.perf_counter() - t1
+        used = a if a >= 0 else 2000
+        line["cpu_baseline"] = {"kind": "oracle", "cores": 1,
+                                "value": used * pop / dt, "unit": "genomes/s",
+                                "sample": f"one simulation at mu L = 0.5, {used} generations"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -389,7 +504,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = all usable cores, at most 16)")
-    ap.add_argument("--workload", choices=("enumeration", "ga", "misclass"),
+    ap.add_argument("--workload", choices=("enumeration", "ga", "misclass", "maps", "fujiyama"),
                     default="enumeration",
                     help="ga: the surrogate-screened GA report; misclass: the classifier's "
                          "error against the true class over S_2,8, R = 1..20")
@@ -420,6 +535,12 @@ def main():
         return
     if args.workload == "misclass":
         misclass_report(args, jt, torch)
+        return
+    if args.workload == "maps":
+        maps_report(args, jt, torch)
+        return
+    if args.workload == "fujiyama":
+        fujiyama_report(args, jt, torch)
         return
     if args.copy_calibration:
         # a blit (copy_) and an elementwise kernel (neg), each reading and

@@ -93,7 +93,9 @@ static int cmp_u32(const void* a, const void* b)
     return (x > y) - (x < y);
 }
 
-uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h)
+/* The first nmaps maps of D4_MAPS: 8 for the dihedral group, 4 (the
+ * rotations, determinant +1) for the rotation group C4 that §3.3 names. */
+static uint32_t shape_hash_group(const uint8_t* mask, int w, int h, int nmaps)
 {
     if (w <= 0 || h <= 0 || w > MAXW || h > MAXW)
         return 0;
@@ -107,7 +109,7 @@ uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h)
     static const int side = MAXW;
     uint8_t* img = (uint8_t*)malloc((size_t)side * side);
     uint8_t* bytes = (uint8_t*)malloc((size_t)2 * n);
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < nmaps; ++k) {
         const int* T = D4_MAPS[k];
         /* transformed coordinates, then shift so the minimum is 0 */
         int minx = 1 << 30, miny = 1 << 30;
@@ -136,12 +138,24 @@ uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h)
     }
     free(img);
     free(bytes);
-    qsort(hashes, 8, sizeof(uint32_t), cmp_u32);
+    qsort(hashes, (size_t)nmaps, sizeof(uint32_t), cmp_u32);
     uint8_t le[32];
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < nmaps; ++k)
         for (int b = 0; b < 4; ++b)
             le[4 * k + b] = (uint8_t)(hashes[k] >> (8 * b));
-    return jref_oaat(le, 32);
+    return jref_oaat(le, 4 * nmaps);
+}
+
+uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h)
+{
+    return shape_hash_group(mask, w, h, 8);
+}
+
+/* Rotations only (§3.3: hash the four orthogonal rotations, sort the hashes
+ * and hash them again): 16 little-endian bytes. */
+uint32_t jref_shape_hash_c4(const uint8_t* mask, int w, int h)
+{
+    return shape_hash_group(mask, w, h, 4);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -349,6 +363,98 @@ static run_out_t run_once(const model_t* m, grid_t* g, int run, uint64_t seed,
     return out;
 }
 
+/* The movelist variant (§3.2): the frontier sites form a LIFO stack.  A
+ * site that joins the frontier (in direction order N, E, S, W of each
+ * update) is inserted at position floor(u * (len + 1) / 2^32) counted from
+ * the bottom of the len sites on the stack, u the next word of the run's
+ * stream (word d of the run for its d-th draw; no word is drawn while the
+ * stack is empty); every step places the pending tile of the site on top. */
+typedef struct {
+    int sites[MAXW * MAXW];
+    int len;
+    int draws;
+    int choice;
+} movelist_t;
+
+static void movelist_insert(movelist_t* ml, int q, const uint32_t key[2], int run,
+                            uint64_t rng_id)
+{
+    int pos = 0;
+    if (ml->len > 0) {
+        uint32_t ctr[4] = { (uint32_t)ml->draws >> 2, (uint32_t)run, (uint32_t)rng_id,
+                            (uint32_t)(rng_id >> 32) };
+        uint32_t words[4];
+        jref_philox4x32_10(ctr, key, words);
+        uint32_t u = words[ml->draws & 3];
+        ml->draws++;
+        ml->choice = 1;
+        pos = (int)(((uint64_t)u * (uint64_t)(ml->len + 1)) >> 32);
+    }
+    for (int i = ml->len; i > pos; --i)
+        ml->sites[i] = ml->sites[i - 1];
+    ml->sites[pos] = q;
+    ml->len++;
+}
+
+/* update() that also pushes every site joining the frontier on the stack. */
+static int update_lifo(const model_t* m, grid_t* g, int p, movelist_t* ml,
+                       const uint32_t key[2], int run, uint64_t rng_id)
+{
+    int before[4], qs[4];
+    int px = p % g->W, py = p / g->W;
+    for (int d = 0; d < 4; ++d) {
+        qs[d] = (py + DY[d]) * g->W + (px + DX[d]);
+        before[d] = g->cell[qs[d]] < 0 && g->pend[qs[d]] < 0;
+    }
+    int ev = update(m, g, p);
+    for (int d = 0; d < 4; ++d)
+        if (before[d] && g->pend[qs[d]] >= 0)
+            movelist_insert(ml, qs[d], key, run, rng_id);
+    return ev;
+}
+
+static run_out_t run_once_lifo(const model_t* m, grid_t* g, int run, uint64_t seed,
+                               uint64_t rng_id, int32_t* trace, int cap, int* ntrace)
+{
+    run_out_t out = { EV_NONE, 0, 0 };
+    int W = g->W;
+    static __thread movelist_t ml;
+    for (int i = 0; i < W * W; ++i) {
+        g->cell[i] = -1;
+        g->pend[i] = -1;
+    }
+    g->nf = 0;
+    ml.len = 0;
+    ml.draws = 0;
+    ml.choice = 0;
+    const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    int centre = (g->G / 2) * W + g->G / 2;
+    g->cell[centre] = (int16_t)m->canon[0];
+    g->size = 1;
+    if (trace && *ntrace < cap)
+        trace[(*ntrace)++] = centre;
+    int ev = update_lifo(m, g, centre, &ml, key, run, rng_id);
+    while (ev == EV_NONE && ml.len > 0) {
+        int p = ml.sites[--ml.len];
+        /* the sorted frontier list mirrors the stack's sites */
+        for (int j = 0; j < g->nf; ++j)
+            if (g->front[j] == p) {
+                frontier_remove_at(g, j);
+                break;
+            }
+        g->cell[p] = g->pend[p];
+        g->pend[p] = -1;
+        g->size++;
+        out.steps++;
+        if (trace && *ntrace < cap)
+            trace[(*ntrace)++] = p;
+        ev = update_lifo(m, g, p, &ml, key, run, rng_id);
+    }
+    out.event = ev;
+    out.choice = ml.choice;
+    return out;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Classification of one genotype (§3.2, §3.3).                              */
 /* ------------------------------------------------------------------------ */
@@ -375,7 +481,7 @@ static int genome_fits(uint64_t genome, int t, int c)
 
 /* Crop an occupancy mask of W*W cells to its bounding box (App. F.6) and
  * hash the cropped shape. */
-static uint32_t hash_of_occupancy(const uint8_t* occ, int W)
+static uint32_t hash_of_occupancy(const uint8_t* occ, int W, int variant)
 {
     int minx = W, miny = W, maxx = -1, maxy = -1;
     for (int y = 0; y < W; ++y)
@@ -393,7 +499,8 @@ static uint32_t hash_of_occupancy(const uint8_t* occ, int W)
     for (int y = 0; y < h; ++y)
         for (int x = 0; x < w; ++x)
             mask[y * w + x] = occ[(y + miny) * W + (x + minx)];
-    uint32_t hv = jref_shape_hash_d4(mask, w, h);
+    uint32_t hv = (variant & JREF_VARIANT_C4) ? jref_shape_hash_c4(mask, w, h)
+                                              : jref_shape_hash_d4(mask, w, h);
     free(mask);
     return hv;
 }
@@ -527,7 +634,7 @@ static int guarded_shape(const model_t* m, const grid_t* g)
 static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome,
                          uint64_t rng_id, int t, int c, int grid, int runs,
                          uint64_t seed, jref_result_t* out, uint8_t* occ_out,
-                         run0_info_t* info0)
+                         run0_info_t* info0, int variant)
 {
     if (jref_check_args(t, c, grid, runs) != JREF_OK || !genome_fits(genome, t, c))
         return JREF_E_INVALID_ARG;
@@ -538,7 +645,9 @@ static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome
     int cells = g->W * g->W;
     int work = 0, size0 = 0;
     for (int r = 0; r < runs; ++r) {
-        run_out_t ro = run_once(&m, g, r, seed, rng_id, NULL, 0, NULL);
+        run_out_t ro = (variant & JREF_VARIANT_LIFO)
+                           ? run_once_lifo(&m, g, r, seed, rng_id, NULL, 0, NULL)
+                           : run_once(&m, g, r, seed, rng_id, NULL, 0, NULL);
         work += ro.steps;
         if (r == 0 && info0) {
             info0->steps = ro.steps;
@@ -576,7 +685,7 @@ static int classify_with(grid_t* g, uint8_t* occ0, uint8_t* occ, uint64_t genome
     }
     out->cls = JREF_DET;
     out->size = size0;
-    out->hash = hash_of_occupancy(occ0, g->W);
+    out->hash = hash_of_occupancy(occ0, g->W, variant);
     out->steps = work;
     if (occ_out)
         memcpy(occ_out, occ0, (size_t)cells);
@@ -596,14 +705,14 @@ int jref_classify_one(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
     if (!ws)
         return JREF_E_INVALID_ARG;
     int rc = classify_with(&ws->g, ws->occ0, ws->occ, genome, rng_id, t, c, grid,
-                           runs, seed, out, occ_out, NULL);
+                           runs, seed, out, occ_out, NULL, 0);
     free(ws);
     return rc;
 }
 
-int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
-                   int run, uint64_t seed, int32_t* cells_out, int cap,
-                   int* event, int* choice)
+int jref_trace_run_variant(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
+                           int run, uint64_t seed, int variant, int32_t* cells_out, int cap,
+                           int* event, int* choice)
 {
     if (jref_check_args(t, c, grid, 1) != JREF_OK || !genome_fits(genome, t, c) || run < 0)
         return JREF_E_INVALID_ARG;
@@ -615,13 +724,23 @@ int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
     ws->g.G = grid;
     ws->g.W = grid + 1;
     int n = 0;
-    run_out_t ro = run_once(&m, &ws->g, run, seed, rng_id, cells_out, cap, &n);
+    run_out_t ro = (variant & JREF_VARIANT_LIFO)
+                       ? run_once_lifo(&m, &ws->g, run, seed, rng_id, cells_out, cap, &n)
+                       : run_once(&m, &ws->g, run, seed, rng_id, cells_out, cap, &n);
     if (event)
         *event = ro.event;
     if (choice)
         *choice = ro.choice;
     free(ws);
     return n;
+}
+
+int jref_trace_run(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
+                   int run, uint64_t seed, int32_t* cells_out, int cap,
+                   int* event, int* choice)
+{
+    return jref_trace_run_variant(genome, rng_id, t, c, grid, run, seed, 0, cells_out, cap,
+                                  event, choice);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -644,6 +763,7 @@ typedef struct {
     int8_t* run0_forced;
     int64_t next;          /* next unclaimed index (atomic)  */
     int error;             /* first error seen (atomic)      */
+    int variant;           /* JREF_VARIANT_* flags           */
 } job_t;
 
 #define CHUNK 4096
@@ -667,7 +787,7 @@ static void* worker(void* arg)
                 const jref_item_t* it = &job->items[i];
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, it->genome, it->rng_id,
                                    it->t, job->c, it->grid, job->runs, job->seed,
-                                   &job->out[i], NULL, NULL);
+                                   &job->out[i], NULL, NULL, job->variant);
             } else {
                 uint64_t g = job->mode == MODE_RANGE ? job->first + (uint64_t)i
                                                      : job->genomes[i];
@@ -675,7 +795,7 @@ static void* worker(void* arg)
                 rc = classify_with(&ws->g, ws->occ0, ws->occ, g,
                                    jref_default_rng_id(g, job->t), job->t, job->c,
                                    job->grid, job->runs, job->seed, &job->out[i], NULL,
-                                   job->run0_steps ? &info : NULL);
+                                   job->run0_steps ? &info : NULL, job->variant);
                 if (job->run0_steps) {
                     job->run0_steps[i] = info.steps;
                     job->run0_event[i] = (int8_t)info.event;
@@ -720,7 +840,7 @@ int jref_classify(const uint64_t* genomes, int64_t n, int t, int c, int grid,
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_LIST, genomes, NULL, 0, n, t, c, grid, runs, seed, out,
-                  NULL, NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -730,7 +850,19 @@ int jref_classify_range(uint64_t first, int64_t n, int t, int c, int grid,
     if (jref_check_args(t, c, grid, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
-                  NULL, NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0, 0 };
+    return run_job(&job, threads);
+}
+
+int jref_classify_variant(const uint64_t* genomes, uint64_t first, int64_t n, int t, int c,
+                          int grid, int runs, uint64_t seed, int variant, jref_result_t* out,
+                          int threads)
+{
+    if (jref_check_args(t, c, grid, runs) != JREF_OK ||
+        (variant & ~(JREF_VARIANT_C4 | JREF_VARIANT_LIFO)) != 0)
+        return JREF_E_INVALID_ARG;
+    job_t job = { genomes ? MODE_LIST : MODE_RANGE, genomes, NULL, first, n, t, c, grid, runs,
+                  seed, out, NULL, NULL, NULL, NULL, 0, 0, variant };
     return run_job(&job, threads);
 }
 
@@ -743,7 +875,7 @@ int jref_classify_range_run0(uint64_t first, int64_t n, int t, int c, int grid,
         !run0_choice || !run0_forced)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_RANGE, NULL, NULL, first, n, t, c, grid, runs, seed, out,
-                  run0_steps, run0_event, run0_choice, run0_forced, 0, 0 };
+                  run0_steps, run0_event, run0_choice, run0_forced, 0, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -753,7 +885,7 @@ int jref_classify_items(const jref_item_t* items, int64_t n, int c, int runs,
     if (jref_check_args(1, c, 16, runs) != JREF_OK)
         return JREF_E_INVALID_ARG;
     job_t job = { MODE_ITEMS, NULL, items, 0, n, 1, c, 16, runs, seed, out,
-                  NULL, NULL, NULL, NULL, 0, 0 };
+                  NULL, NULL, NULL, NULL, 0, 0, 0 };
     return run_job(&job, threads);
 }
 
@@ -899,7 +1031,7 @@ static int explore_all(const model_t* m, grid_t* g, int64_t cap, state_set_t* s,
     for (int64_t k = 0; k < s->n; ++k)   /* empty the table for the next genotype */
         s->slot[s->slot_of[k]] = 0;
     *size_out = verdict == TRUTH_DET ? term_size : 0;
-    *hash_out = verdict == TRUTH_DET ? hash_of_occupancy(term, W) : 0;
+    *hash_out = verdict == TRUTH_DET ? hash_of_occupancy(term, W, 0) : 0;
     free(cur);
     free(nxt);
     return verdict;

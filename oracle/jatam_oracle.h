@@ -75,6 +75,23 @@ uint64_t jref_default_rng_id(uint64_t genome, int t);
 /* D4-invariant hash of a shape given as a w*h row-major byte mask (nonzero =
  * occupied).  Returns 0 for an empty mask. */
 uint32_t jref_shape_hash_d4(const uint8_t* mask, int w, int h);
+/* The same over the four rotations only (C4). */
+uint32_t jref_shape_hash_c4(const uint8_t* mask, int w, int h);
+
+/* Classification variants (NEXT to the uniform traversal and the D4 hash):
+ * JREF_VARIANT_C4 hashes DET shapes up to rotation only; JREF_VARIANT_LIFO
+ * grows by the LIFO movelist with random insertion (§3.2). */
+enum { JREF_VARIANT_C4 = 1, JREF_VARIANT_LIFO = 2 };
+
+/* genomes, or NULL for the range first + i; variant flags as above. */
+int jref_classify_variant(const uint64_t* genomes, uint64_t first, int64_t n, int t, int c,
+                          int grid, int runs, uint64_t seed, int variant, jref_result_t* out,
+                          int threads);
+
+/* jref_trace_run with a traversal variant. */
+int jref_trace_run_variant(uint64_t genome, uint64_t rng_id, int t, int c, int grid,
+                           int run, uint64_t seed, int variant, int32_t* cells_out, int cap,
+                           int* event, int* choice);
 
 /* Checks the arguments of a classification call. */
 int jref_check_args(int t, int c, int grid, int runs);

@@ -110,6 +110,61 @@ def shape_hash_d4(mask: np.ndarray) -> int:
     return int(lib().jref_shape_hash_d4(m.ctypes.data, w, h))
 
 
+def shape_hash_c4(mask: np.ndarray) -> int:
+    """Shape hash over the four rotations only (§3.3)."""
+    L = lib()
+    L.jref_shape_hash_c4.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.jref_shape_hash_c4.restype = ctypes.c_uint32
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = m.shape
+    return int(L.jref_shape_hash_c4(m.ctypes.data, w, h))
+
+
+VARIANT_C4, VARIANT_LIFO = 1, 2
+
+
+def classify_variant(genomes, t: int, variant: int, c: int = 8, grid: int = 16, runs: int = 20,
+                     seed: int = 1, first: int = 0, n: int | None = None,
+                     threads: int = 0) -> np.ndarray:
+    """Classification with the C4 hash and/or the LIFO movelist traversal;
+    genomes None means the range first .. first + n - 1."""
+    L = lib()
+    L.jref_classify_variant.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int]
+    L.jref_classify_variant.restype = ctypes.c_int
+    g = None if genomes is None else np.ascontiguousarray(genomes, dtype=np.uint64)
+    n = len(g) if g is not None else n
+    out = np.zeros(n, dtype=RECORD)
+    rc = L.jref_classify_variant(g.ctypes.data if g is not None else None, first, n, t, c, grid,
+                                 runs, seed, variant, out.ctypes.data, threads)
+    if rc != 0:
+        raise ValueError(f"oracle rejected arguments (rc={rc})")
+    return out
+
+
+def trace_run_variant(genome: int, t: int, run: int, variant: int, c: int = 8, grid: int = 16,
+                      seed: int = 1, rng_id: int | None = None):
+    """trace_run with a traversal variant."""
+    L = lib()
+    L.jref_trace_run_variant.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.jref_trace_run_variant.restype = ctypes.c_int
+    rid = default_rng_id(genome, t) if rng_id is None else rng_id
+    cap = (grid + 1) * (grid + 1)
+    cells = np.zeros(cap, dtype=np.int32)
+    ev, ch = ctypes.c_int(0), ctypes.c_int(0)
+    n = L.jref_trace_run_variant(genome, rid, t, c, grid, run, seed, variant, cells.ctypes.data,
+                                 cap, ctypes.byref(ev), ctypes.byref(ch))
+    if n < 0:
+        raise ValueError("oracle rejected arguments")
+    W = grid + 1
+    return [(int(p) % W, int(p) // W) for p in cells[:n]], int(ev.value), int(ch.value)
+
+
 def check_args(t: int, c: int, grid: int, runs: int) -> int:
     return int(lib().jref_check_args(t, c, grid, runs))
 

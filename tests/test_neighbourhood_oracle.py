@@ -29,7 +29,7 @@ def shape_hash(cells):
     return ref.shape_hash_d4(m)
 
 
-def fixed_phenotype(genome, t, c=8, grid=16, cap=3000):
+def fixed_phenotype(genome, t, c=8, grid=16, cap=800):
     """('DET', size, hash), ('UNBOUND',), ('ND',) or None when the outcome
     depends on the random stream (two different outcomes are reachable) or
     more than `cap` configurations would have to be visited to tell.
@@ -126,10 +126,10 @@ def test_s18_robustness_and_evolvability_match_brute_force():
 
 def test_s28_sample_robustness_and_evolvability_match_brute_force():
     rng = np.random.default_rng(8)
-    g = rng.integers(0, 1 << 24, size=300, dtype=np.uint64)
+    g = rng.integers(0, 1 << 24, size=200, dtype=np.uint64)
     robust, evolv = ref.neighbourhood(g, 2)
     want = brute_counts(g, 2)
-    assert len(want) > 100
+    assert len(want) > 60
     idx = {int(x): i for i, x in enumerate(g)}
     for k, (r, e) in want.items():
         assert (robust[idx[k]], evolv[idx[k]]) == (r, e), k
