@@ -5,7 +5,8 @@ One step = classification of all 2^24 two-tile genotypes (c=8, G=16, R=20,
 seed 1), no input read from HBM, 256 MiB of records written to HBM.  Four
 paths are timed on the same stream:
   plain      16 launches of the plain kernel over 2^20-genotype ranges,
-  graph      one captured pipeline of a 2^20-genotype slice, replayed 16 times,
+  graph      one captured pipeline of a 2^20-genotype slice, replayed 16 times
+             (and of a 2^22 slice, replayed 4 times),
   surrogate  the trained network's predicted cost of every genotype, the
              queue ordered by it, the pipelined call in that order (scoring
              and ordering inside the timed step),
@@ -496,6 +497,81 @@ def fujiyama_report(args, jt, torch):
     print(json.dumps(line), flush=True)
 
 
+def space_report(args, jt, torch):
+    """Whole-space enumerations (sections 4.1-4.3): every genotype of the
+    three-tile space S_{3,8} (8^12) at G=32, R=20 in graph-replayed slices
+    of 2^26 (class tally and the D4 shape histogram kept, records dropped),
+    and the paper's subset S^32_{3,8} (genome = k << 4, k < 2^32: the last
+    tile's W colour 0 and its low S bit 0) at R=7 with the D4 histogram
+    and, for its deterministic genotypes, the C4 (rotation-only) shape
+    count.  Prints one JSON line."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    slice_n = 1 << 26
+    grid = 32
+    if "full" in args.spaces:
+        total = 8 ** 12
+        slices = total // slice_n
+        tally = torch.zeros(4, dtype=torch.int64, device=dev)
+        shapes = torch.zeros((1 << 22, 2), dtype=torch.int64, device=dev)
+        with jt.Batch(slice_n) as b:
+            b.enumerate(0, slice_n, 1, 3, C, grid, RUNS, SEED)          # warm-up, untimed
+            tally.zero_()
+            shapes.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.enumerate(0, slice_n, slices, 3, C, grid, RUNS, SEED, tally=tally, shapes=shapes,
+                        stream=stream)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+        tab = jt.shape_table_to_numpy(shapes)
+        res["s38_full"] = {"genotypes": total, "grid": grid, "runs": RUNS, "seconds": secs,
+                           "genotypes_per_s": total / secs,
+                           "tally": dict(zip(["unbound", "nd_site", "nd_runs", "det"],
+                                             tally.cpu().tolist())),
+                           "distinct_det_shapes": int(len(tab)),
+                           "largest_det_size": int(tab["size"].max()) if len(tab) else 0}
+        del shapes
+    if "subset" in args.spaces:
+        runs7, total = 7, 1 << 32
+        tally = torch.zeros(4, dtype=torch.int64, device=dev)
+        shapes = torch.zeros((1 << 20, 2), dtype=torch.int64, device=dev)
+        c4_keys = set()
+        secs = 0.0
+        c4_secs = 0.0
+        with jt.Batch(slice_n) as b:
+            for lo in range(0, total, slice_n):
+                g = (torch.arange(lo, lo + slice_n, dtype=torch.int64, device=dev) << 4)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rec = b.classify(g, 3, C, grid, runs7, SEED, tally=tally)
+                jt.shape_histogram(rec, shapes)
+                torch.cuda.synchronize()
+                secs += time.perf_counter() - t0
+                det = g[rec[:, 0] == 3].contiguous()
+                t1 = time.perf_counter()
+                rc4 = jt.classify_variant(det, 3, jt.VARIANT_C4, grid_limit=grid, runs=runs7)
+                keys = torch.unique((rc4[:, 1].to(torch.int64) << 32) |
+                                    (rc4[:, 2].to(torch.int64) & 0xFFFFFFFF))
+                torch.cuda.synchronize()
+                c4_secs += time.perf_counter() - t1
+                c4_keys.update(keys.cpu().tolist())
+        tab = jt.shape_table_to_numpy(shapes)
+        res["paper_subset_s32"] = {"genotypes": total, "grid": grid, "runs": runs7,
+                                   "seconds": secs, "genotypes_per_s": total / secs,
+                                   "tally": dict(zip(["unbound", "nd_site", "nd_runs", "det"],
+                                                     tally.cpu().tolist())),
+                                   "distinct_det_shapes_d4": int(len(tab)),
+                                   "distinct_det_shapes_c4": len(c4_keys),
+                                   "c4_pass_seconds": c4_secs,
+                                   "paper_count_context": 361}
+    print(json.dumps({"metric": "whole-space enumerations of the three-tile space",
+                      "n_gpus": 1, "data": "exhaustive enumeration", "results": res}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -504,13 +580,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = all usable cores, at most 16)")
-    ap.add_argument("--workload", choices=("enumeration", "ga", "misclass", "maps", "fujiyama"),
+    ap.add_argument("--workload", choices=("enumeration", "ga", "misclass", "maps", "fujiyama",
+                             "spaces"),
                     default="enumeration",
                     help="ga: the surrogate-screened GA report; misclass: the classifier's "
                          "error against the true class over S_2,8, R = 1..20")
     ap.add_argument("--generations", type=int, default=500)
     ap.add_argument("--paths", default="plain,graph,surrogate,batched",
                     help="comma-separated subset of the timed paths (batched is always timed)")
+    ap.add_argument("--spaces", default="full,subset",
+                    help="spaces workload: full (8^12 at G=32) and/or subset (the paper's "
+                         "S^32_3,8 at R=7)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch parameters")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -541,6 +621,9 @@ def main():
         return
     if args.workload == "fujiyama":
         fujiyama_report(args, jt, torch)
+        return
+    if args.workload == "spaces":
+        space_report(args, jt, torch)
         return
     if args.copy_calibration:
         # a blit (copy_) and an elementwise kernel (neg), each reading and
@@ -578,10 +661,7 @@ def main():
     def batched_step():
         batch.classify_range(0, TOTAL, T, C, GRID, RUNS, SEED, out=out, stream=stream)
 
-    graph_batch = jt.Batch(SLICE)
-
-    def graph_step():
-        graph_batch.enumerate(0, SLICE, nslices, T, C, GRID, RUNS, SEED, out=out, stream=stream)
+    graph_batch = jt.Batch(4 * SLICE)
 
     def verify():
         rec = out.cpu().numpy()
@@ -644,20 +724,30 @@ def main():
     tuning, tune_log = (batch.get_tuning(GRID), []) if args.no_autotune else \
         batch.autotune(0, TOTAL, T, C, GRID, RUNS, TUNE_SEED)
 
-    # graph path: one captured 2^20-genotype slice pipeline, replayed 16
-    # times; its workspace is tuned for the slice it replays (a 2^20 slice
-    # leaves each of the one-call grid's waves only a few chunks)
+    # graph paths: one captured slice pipeline (2^20 or 2^22 genotypes),
+    # replayed 16 or 4 times; the workspace is tuned for the slice it
+    # replays (a 2^20 slice leaves each of the one-call grid's waves only a
+    # few chunks)
     if "graph" in paths:
-        graph_tuning = graph_batch.get_tuning(GRID) if args.no_autotune else \
-            graph_batch.autotune(0, SLICE, T, C, GRID, RUNS, TUNE_SEED)[0]
-        graph_total_ms, _ = timed(graph_step, graph_step)
-        graph_ok = verify()
-        bit_exact &= graph_ok
-        results["graph"] = {
-            "value": TOTAL * args.steps / (graph_total_ms / 1e3),
-            "ms_per_step": graph_total_ms / args.steps, "bit_exact": graph_ok,
-            "tuning": graph_tuning,
-            "kernel": "one captured 2^20-genotype slice pipeline, 16 hipGraph replays"}
+        for slice_n in (SLICE, 4 * SLICE):
+            reps = TOTAL // slice_n
+
+            def graph_step():
+                graph_batch.enumerate(0, slice_n, reps, T, C, GRID, RUNS, SEED, out=out,
+                                      stream=stream)
+
+            graph_tuning = graph_batch.get_tuning(GRID) if args.no_autotune else \
+                graph_batch.autotune(0, slice_n, T, C, GRID, RUNS, TUNE_SEED)[0]
+            graph_total_ms, _ = timed(graph_step, graph_step)
+            graph_ok = verify()
+            bit_exact &= graph_ok
+            name = "graph" if slice_n == SLICE else "graph_2e22"
+            results[name] = {
+                "value": TOTAL * args.steps / (graph_total_ms / 1e3),
+                "ms_per_step": graph_total_ms / args.steps, "bit_exact": graph_ok,
+                "tuning": graph_tuning,
+                "kernel": f"one captured 2^{slice_n.bit_length() - 1}-genotype slice pipeline, "
+                          f"{reps} hipGraph replays"}
     graph_batch.close()
 
     # batched + surrogate path: the network (trained untimed, on genotypes

@@ -82,6 +82,7 @@ enum {
     JATAM_E_UNSUPPORTED = -2, /* valid model, not built for this grid size     */
     JATAM_E_HIP = -3,         /* a HIP launch or runtime call failed           */
     JATAM_E_MISMATCH = -4,    /* autotuning: a candidate's records differed    */
+    JATAM_E_IO = -5,          /* a file could not be read or written           */
 };
 
 /*
@@ -249,11 +250,15 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *   claim_chunks  first runs: the most 64-item chunks one claim takes
  *                 (1..8; default 4): the work queue's chunk size.
  *   repeat_mapping  repeat runs of the candidates that run 0 leaves
- *                 undecided: 0 (default) gives each candidate R lanes of a
+ *                 undecided (default 2 for G <= 16, 0 above): 0 gives each
+ *                 candidate R lanes of a
  *                 wave, lane r making run r; 1 gives each candidate one
  *                 lane that makes runs 1, 2, ... in turn and stops at the
  *                 first witness, a lane that finishes taking the next
- *                 candidate from the queue.
+ *                 candidate from the queue; 2 makes two passes, the first
+ *                 with 4 lanes per candidate (runs 0..3: a witness among
+ *                 them decides), the second with R lanes for the
+ *                 candidates the first left undecided.
  */
 typedef struct {
     int refill;
@@ -319,8 +324,8 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
  * from the current parameters it tries, one field at a time, refill in
  * {8, 16, 24, 32, 48}, first_waves and repeat_waves at and below the
  * residency limit, every wide_layout value of the class, claim_share in
- * {0, 4, 8, 12, 16}, claim_chunks in {1, 2, 4, 8} and both repeat_mapping
- * values, keeping a
+ * {0, 4, 8, 12, 16}, claim_chunks in {1, 2, 4, 8} and the three
+ * repeat_mapping values, keeping a
  * value when the median of three timed calls improves by more than 1%
  * (less is within run-to-run noise).  Every candidate's records are
  * compared with the starting configuration's, bit for bit: a difference
@@ -332,6 +337,24 @@ int jatam_batch_set_tuning(jatam_batch_t* batch, int grid_limit, const jatam_tun
 int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t, int c,
                          int grid_limit, int runs, uint64_t seed, jatam_result_t* scratch,
                          jatam_tuning_t* best, void* stream);
+
+/*
+ * jatam_batch_autotune with a cache file, so the search runs once per
+ * device and workload class: the file holds one JSON object per line,
+ *   {"key": "<gfx arch>|cu<CUs>|G<16|32>|t<t>|c<c>|R<runs>|abi<version>",
+ *    "refill": .., "first_waves": .., "repeat_waves": .., "wide_layout": ..,
+ *    "claim_share": .., "claim_chunks": .., "repeat_mapping": ..}
+ * keyed by the device, grid_limit's class, t, c and runs.  A valid entry
+ * for the key is applied (jatam_batch_set_tuning) and *from_cache = 1;
+ * otherwise jatam_batch_autotune runs (arguments as there) and the file is
+ * rewritten with the new entry added (other keys kept, a broken line of this
+ * key dropped; written to path.tmp, then renamed), *from_cache = 0.
+ * JATAM_E_IO if the file cannot be written.  Not thread-safe on one file.
+ */
+int jatam_batch_autotune_cached(jatam_batch_t* batch, const char* path, uint64_t first,
+                                int64_t n, int t, int c, int grid_limit, int runs,
+                                uint64_t seed, jatam_result_t* scratch, jatam_tuning_t* best,
+                                int* from_cache, void* stream);
 
 /* Entry i of the last autotune's log (the configuration and its median ms);
  * returns the number of entries (i < 0: only that). */
@@ -589,6 +612,30 @@ int jatam_true_class(jatam_truth_t* w, const uint64_t* genotypes, int64_t n, int
 /* Same for the range genome_i = first + i. */
 int jatam_true_class_range(jatam_truth_t* w, uint64_t first, int64_t n, int t, int c,
                            int grid_limit, int64_t cap, jatam_result_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Classification variants, by the plain kernel (one lane per genotype):
+ *   JATAM_VARIANT_C4    DET shapes hashed up to rotation only (§3.3 names the
+ *                       four rotations): the four rotation hashes sorted
+ *                       ascending and hashed again as 16 little-endian bytes
+ *   JATAM_VARIANT_LIFO  the movelist traversal of §3.2: frontier sites on a
+ *                       LIFO stack; a site that joins the frontier (in the
+ *                       order N, E, S, W of each placement's checks) goes to
+ *                       slot floor(u (len + 1) / 2^32) from the bottom of the
+ *                       len sites on the stack, u the run's next random word
+ *                       (word d of the run's stream for its d-th draw; no
+ *                       draw into an empty stack); each step places the site
+ *                       on top.  A run without a draw is the only run.
+ *                       G <= 16 only (JATAM_E_UNSUPPORTED above).
+ * The flags combine; 0 gives jatam_classify's records.  genotypes: device
+ * array, or NULL for the range genotype_i = first + i.  Other arguments and
+ * errors as jatam_classify.
+ * ------------------------------------------------------------------------ */
+enum { JATAM_VARIANT_C4 = 1, JATAM_VARIANT_LIFO = 2 };
+
+int jatam_classify_variant(const uint64_t* genotypes, uint64_t first, int64_t n, int t, int c,
+                           int grid_limit, int runs, uint64_t seed, int variant,
+                           jatam_result_t* out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Robustness and evolvability (§1.1): robustness is the share of a

@@ -3,8 +3,13 @@
 // allocates (its workspace); no exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "jatam_internal.hpp"
@@ -51,7 +56,7 @@ bool tuning_valid(int grid_limit, const jatam_tuning_t* t)
            t->wide_layout >= 0 && t->wide_layout <= (grid_limit > 16 ? 2 : 1) &&
            t->claim_share >= 0 && t->claim_share <= 16 && t->claim_chunks >= 1 &&
            t->claim_chunks <= jatam::kMaxClaimChunks && t->repeat_mapping >= 0 &&
-           t->repeat_mapping <= 1;
+           t->repeat_mapping <= 2;
 }
 
 // Candidate values of one tuning field, around the residency limit `occ`.
@@ -78,6 +83,7 @@ const char* jatam_strerror(int code)
     case JATAM_E_UNSUPPORTED: return "unsupported configuration";
     case JATAM_E_HIP: return "HIP runtime error";
     case JATAM_E_MISMATCH: return "a launch configuration changed the records";
+    case JATAM_E_IO: return "a file could not be read or written";
     default: return "unknown error";
     }
 }
@@ -112,6 +118,25 @@ int jatam_classify_range(uint64_t first, int64_t n, int t, int c, int grid_limit
             return JATAM_E_INVALID_ARG;
     }
     return jatam::launch_plain(nullptr, first, n, p, out, (hipStream_t)stream);
+}
+
+int jatam_classify_variant(const uint64_t* genotypes, uint64_t first, int64_t n, int t, int c,
+                           int grid_limit, int runs, uint64_t seed, int variant,
+                           jatam_result_t* out, void* stream)
+{
+    jatam::Params p;
+    const int rc = jatam::make_params(t, c, grid_limit, runs, seed, &p);
+    if (rc != JATAM_OK)
+        return rc;
+    if (n < 0 || (n > 0 && out == nullptr) ||
+        (variant & ~(JATAM_VARIANT_C4 | JATAM_VARIANT_LIFO)) != 0)
+        return JATAM_E_INVALID_ARG;
+    if (n > 0 && genotypes == nullptr) {
+        const uint64_t last = first + (uint64_t)(n - 1);
+        if (last < first || (p.genome_bits < 64 && (last >> p.genome_bits) != 0))
+            return JATAM_E_INVALID_ARG;
+    }
+    return jatam::launch_variant(genotypes, first, n, p, variant, out, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -214,7 +239,7 @@ int jatam_batch_create(int64_t max_n, jatam_batch_t** batch)
     b->graph_exec = nullptr;
     b->graph_stream = nullptr;
     for (int k = 0; k < 2; ++k)
-        b->tune[k] = jatam::default_tuning();
+        b->tune[k] = jatam::default_tuning(k);
     hipDeviceProp_t prop;
     if (hipGetDevice(&b->device) != hipSuccess ||
         hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
@@ -578,7 +603,7 @@ int jatam_batch_autotune(jatam_batch_t* batch, uint64_t first, int64_t n, int t,
         else if (field == 5)
             choices = {1, 2, 4, 8};
         else if (field == 6)
-            choices = {0, 1};
+            choices = {0, 1, 2};
         else if (field == 1)
             choices = wave_choices(batch->occ[k][ti][0]);
         else if (field == 2)
@@ -623,6 +648,76 @@ done:
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Autotune cache: one JSON object per line,
+//   {"key": "<arch>|cu<n>|G<16|32>|t<t>|c<c>|R<runs>|abi<v>", "refill": .., ...}
+// ---------------------------------------------------------------------------
+namespace {
+
+const char* const kTuningFields[7] = {"refill",      "first_waves",  "repeat_waves",
+                                      "wide_layout", "claim_share",  "claim_chunks",
+                                      "repeat_mapping"};
+
+int* tuning_field(jatam_tuning_t* t, int i)
+{
+    int* const f[7] = {&t->refill,      &t->first_waves,  &t->repeat_waves, &t->wide_layout,
+                       &t->claim_share, &t->claim_chunks, &t->repeat_mapping};
+    return f[i];
+}
+
+std::string tuning_key(const jatam_batch_t* batch, int t, int c, int grid_limit, int runs)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, batch->device) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == '"' || ch == '|' || ch == '\\' || (unsigned char)ch < 32)
+            ch = '_';
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|cu%d|G%d|t%d|c%d|R%d|abi%d", arch.c_str(), batch->cus,
+             grid_limit <= 16 ? 16 : 32, t, c, runs, jatam_abi_version());
+    return buf;
+}
+
+// The tuning stored under `key` in one line of the file, if the line holds it
+// whole and valid.
+bool parse_tuning_line(const char* line, const std::string& key, int grid_limit,
+                       jatam_tuning_t* out)
+{
+    const std::string want = "\"key\": \"" + key + "\"";
+    if (strstr(line, want.c_str()) == nullptr)
+        return false;
+    jatam_tuning_t t{};
+    for (int i = 0; i < 7; ++i) {
+        const std::string name = std::string("\"") + kTuningFields[i] + "\":";
+        const char* at = strstr(line, name.c_str());
+        if (at == nullptr)
+            return false;
+        char* end = nullptr;
+        const long v = strtol(at + name.size(), &end, 10);
+        if (end == at + name.size() || v < -1000000 || v > 1000000)
+            return false;
+        *tuning_field(&t, i) = (int)v;
+    }
+    if (!tuning_valid(grid_limit, &t))
+        return false;
+    *out = t;
+    return true;
+}
+
+std::string tuning_line(const std::string& key, const jatam_tuning_t& t)
+{
+    std::string line = "{\"key\": \"" + key + "\"";
+    jatam_tuning_t c = t;
+    for (int i = 0; i < 7; ++i)
+        line += std::string(", \"") + kTuningFields[i] + "\": " +
+                std::to_string(*tuning_field(&c, i));
+    return line + "}";
+}
+
+}  // namespace
+
 int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* tuning, double* ms)
 {
     if (batch == nullptr)
@@ -635,6 +730,67 @@ int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* 
     *tuning = batch->tune_log[(size_t)i].first;
     *ms = batch->tune_log[(size_t)i].second;
     return count;
+}
+
+int jatam_batch_autotune_cached(jatam_batch_t* batch, const char* path, uint64_t first,
+                                int64_t n, int t, int c, int grid_limit, int runs,
+                                uint64_t seed, jatam_result_t* scratch, jatam_tuning_t* best,
+                                int* from_cache, void* stream)
+{
+    if (batch == nullptr || path == nullptr || grid_limit < 8 || grid_limit > 32)
+        return JATAM_E_INVALID_ARG;
+    const std::string key = tuning_key(batch, t, c, grid_limit, runs);
+    std::vector<std::string> lines;
+    jatam_tuning_t found{};
+    bool have = false;
+    if (FILE* f = fopen(path, "r")) {
+        char buf[1024];
+        while (fgets(buf, sizeof(buf), f) != nullptr) {
+            std::string line(buf);
+            while (!line.empty() && (line.back() == '\n' || line.back() == '\r'))
+                line.pop_back();
+            if (line.empty())
+                continue;
+            if (!have && parse_tuning_line(line.c_str(), key, grid_limit, &found)) {
+                have = true;
+                continue;   // rewritten below
+            }
+            if (line.find("\"key\": \"" + key + "\"") == std::string::npos)
+                lines.push_back(line);   // other keys are kept; a broken line of this key is not
+        }
+        fclose(f);
+    }
+    if (have) {
+        const int rc = jatam_batch_set_tuning(batch, grid_limit, &found);
+        if (rc != JATAM_OK)
+            return rc;
+        if (best != nullptr)
+            *best = found;
+        if (from_cache != nullptr)
+            *from_cache = 1;
+        return JATAM_OK;
+    }
+    jatam_tuning_t tuned{};
+    const int rc = jatam_batch_autotune(batch, first, n, t, c, grid_limit, runs, seed, scratch,
+                                        &tuned, stream);
+    if (rc != JATAM_OK)
+        return rc;
+    lines.push_back(tuning_line(key, tuned));
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (f == nullptr)
+        return JATAM_E_IO;
+    bool ok = true;
+    for (const std::string& line : lines)
+        ok = ok && fprintf(f, "%s\n", line.c_str()) > 0;
+    ok = fclose(f) == 0 && ok;
+    if (!ok || rename(tmp.c_str(), path) != 0)
+        return JATAM_E_IO;
+    if (best != nullptr)
+        *best = tuned;
+    if (from_cache != nullptr)
+        *from_cache = 0;
+    return JATAM_OK;
 }
 
 int jatam_batch_set_timing(jatam_batch_t* batch, int enable)
@@ -1102,7 +1258,13 @@ extern "C" int jatam_shape_histogram(const jatam_result_t* recs, int64_t n,
 // ---------------------------------------------------------------------------
 namespace jatam {
 
-jatam_tuning_t default_tuning() { return jatam_tuning_t{24, 64, 64, 0, 8, 4, 0}; }
+// Class 0 (G <= 16) makes its repeat runs in two passes (on S_2,8 most
+// candidates left after the proofs are non-deterministic and decided by run
+// 1, 2 or 3); class 1 in one (large deterministic shapes need every run).
+jatam_tuning_t default_tuning(int klass)
+{
+    return jatam_tuning_t{24, 64, 64, 0, 8, 4, klass == 0 ? 2 : 0};
+}
 
 int max_first_blocks(const int occ[2][2][3], int cus)
 {

@@ -103,9 +103,13 @@ struct RunState {
 // Invariant: the PEND nibble of a free cell is zero unless the cell is on
 // the frontier, so a new pending tile is written with one LDS atomic OR.  An
 // occupied cell keeps the tile placed there in its nibble.
+//
+// `added`, if given, receives bit d for every direction d whose site joined
+// the frontier (the movelist traversal pushes those sites).
 template <int W, int B, class Src>
 __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
-                                           int G, int p, uint32_t tuple)
+                                           int G, int p, uint32_t tuple,
+                                           uint32_t* added = nullptr)
 {
     constexpr int kMask = W * W - 1;
     uint32_t opt[4], ow[4], fw[4], pw[4];
@@ -146,6 +150,8 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
             LaneGrid<W, B>::set_bits(g.pend_word(q[d]), id << sh);
             st.fsum |= 1u << (q[d] >> 5);
             st.nf += 1;
+            if (added != nullptr)
+                *added |= 1u << d;
         }
     }
     return unbound ? kEvUnbound : ambiguous ? kEvAmbig : kEvNone;
@@ -870,6 +876,140 @@ struct ShapeCache {
         wave_lds_sync();
     }
 };
+
+// The 4 rotation hashes sorted ascending, hashed again as 16 little-endian
+// bytes (§3.3's rotation-invariant hash).
+__device__ __forceinline__ uint32_t combine_rotations(uint32_t hs[4])
+{
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+#pragma unroll
+        for (int i = pass & 1; i + 1 < 4; i += 2) {
+            const uint32_t a = hs[i], b = hs[i + 1];
+            hs[i] = a < b ? a : b;
+            hs[i + 1] = a < b ? b : a;
+        }
+    }
+    uint32_t hv = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            hv = oaat_add(hv, (hs[i] >> (8 * b)) & 0xFFu);
+    return oaat_finish(hv);
+}
+
+// C4-invariant hash of the shape held in OCC: orientations 0 (identity),
+// 3 (both mirrors: the half turn), 5 and 6 (a transpose and one mirror: the
+// quarter turns) of the dihedral images, computed by one lane.
+template <int W, int B>
+__device__ uint32_t shape_hash_c4(LaneGrid<W, B>& g, int G)
+{
+    constexpr int kRot[4] = {0, 3, 5, 6};
+    uint32_t hs[4];
+    uint64_t m;
+    int w, h;
+    if (shape_bitmap8(g, G, m, w, h)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            hs[k] = bitmap_hash8(image8(m, w, h, kRot[k]));
+    } else {
+        const ShapeBox bx = crop(g, G);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            hs[k] = orientation_hash(g, bx, kRot[k]);
+    }
+    return combine_rotations(hs);
+}
+
+// ---------------------------------------------------------------------------
+// The movelist traversal (§3.2): the frontier sites on a LIFO stack of cell
+// indices (bytes, after the lane's grid words, 16 x 16 layout only).  A site
+// that joins the frontier (directions N, E, S, W of each update) goes to slot
+// floor(u (len + 1) / 2^32) counted from the bottom of the len sites on the
+// stack, u the run's next word (word d for its d-th draw; none while the
+// stack is empty); every step places the site on top.
+// ---------------------------------------------------------------------------
+constexpr int kStackWords = 64;   // 256 one-byte entries >= the 225 cells of the box
+
+template <int B>
+struct LaneStack {
+    uint32_t* base;   // the lane's first stack word (word k at base[k * B])
+
+    __device__ __forceinline__ uint8_t* byte(int i)
+    {
+        return reinterpret_cast<uint8_t*>(base + (i >> 2) * B) + (i & 3);
+    }
+    __device__ __forceinline__ int get(int i) { return *byte(i); }
+    __device__ __forceinline__ void set(int i, int v) { *byte(i) = (uint8_t)v; }
+};
+
+// Pushes the sites of the directions in `added` (in order N, E, S, W) next to
+// p; len is the stack's length before them.  Returns the new length.
+template <int W, int B, class Draws>
+__device__ __forceinline__ uint32_t movelist_push(LaneStack<B>& stk, uint32_t len, int p,
+                                                  uint32_t added, Draws& dc, uint32_t& draws,
+                                                  bool& choice, int run, uint32_t key0,
+                                                  uint32_t key1, uint32_t rid_lo, uint32_t rid_hi)
+{
+    constexpr int kMask = W * W - 1;
+    for (int d = 0; d < 4; ++d) {
+        if (((added >> d) & 1u) == 0u)
+            continue;
+        const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
+        const int q = (p + delta) & kMask;
+        uint32_t pos = 0;
+        if (len > 0u) {
+            pos = __umulhi(dc.draw(draws, run, key0, key1, rid_lo, rid_hi), len + 1u);
+            draws += 1;
+            choice = true;
+        }
+        for (uint32_t i = len; i > pos; --i)
+            stk.set((int)i, stk.get((int)i - 1));
+        stk.set((int)pos, q);
+        len += 1;
+    }
+    return len;
+}
+
+// One run with the movelist traversal, from the seed to completion or an
+// event (st.nf is the stack's length throughout).
+template <int W, int B, class Src>
+__device__ __forceinline__ int run_assembly_lifo(const Src& m, LaneGrid<W, B>& g,
+                                                 LaneStack<B>& stk, RunState& st, int G, int run,
+                                                 uint32_t key0, uint32_t key1, uint32_t rid_lo,
+                                                 uint32_t rid_hi)
+{
+    DrawCache dc;
+    const int seed_pos = run_clear(g, st, dc, G);
+    uint32_t draws = 0, added = 0;
+    bool choice = false;
+    int ev = update_site(m, g, st, G, seed_pos, m.seed(), &added);
+    movelist_push<W>(stk, 0u, seed_pos, added, dc, draws, choice, run, key0, key1, rid_lo,
+                     rid_hi);
+    while (ev == kEvNone && st.nf > 0 && st.steps < (G - 1) * (G - 1)) {
+        const int p = stk.get((int)st.nf - 1);
+        st.nf -= 1;
+        const int w = p >> 5;
+        const uint32_t fw = g.fr(w) & ~(1u << (p & 31));
+        g.fr(w) = fw;
+        if (fw == 0)
+            st.fsum &= ~(1u << w);
+        const uint32_t pw = g.pend_word(p);
+        const uint32_t sh = ((uint32_t)p & 7u) * 4u;
+        const uint32_t tuple = m.oriented((int)((pw >> sh) & 15u));
+        LaneGrid<W, B>::set_bits(g.occ(w), 1u << (p & 31));
+        st.osum |= 1u << w;
+        st.size += 1;
+        st.steps += 1;
+        const uint32_t len = st.nf;
+        added = 0;
+        ev = update_site(m, g, st, G, p, tuple, &added);
+        movelist_push<W>(stk, len, p, added, dc, draws, choice, run, key0, key1, rid_lo, rid_hi);
+    }
+    st.choice = choice;
+    return ev;
+}
 
 // D4-invariant hash of the shape held in OCC, computed by one lane.
 template <int W, int B>

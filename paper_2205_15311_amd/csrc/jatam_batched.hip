@@ -746,8 +746,18 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
     return v;
 }
 
+//
+// With rpass < R (the first of two passes) a group of rpass lanes makes runs
+// 0 .. rpass-1 of its candidate: a witness among them decides the record as
+// above; a candidate without one goes to queue_out (count_out counts them)
+// for the second pass, rpass = R, which makes all of its runs.  Most
+// non-deterministic candidates are decided by run 1, 2 or 3, so the first
+// pass spares most of the runs a single pass would make.
 template <int W, int TM, bool kTable>
-__global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass)
+__global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass, int rpass,
+                                                    const uint32_t* queue_in,
+                                                    const uint32_t* count_in,
+                                                    uint32_t* queue_out, uint32_t* count_out)
 {
     using Geo = Geometry<W>;
     const uint64_t first = slice_first(a);
@@ -763,7 +773,8 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
     RunState st{0, 0, 0, 0, 0, false};
     WaveTally tally{{0, 0, 0, 0}};
 
-    const int R = a.runs;
+    const int R = rpass;                              // runs made in this pass
+    const bool all_runs = rpass >= a.runs;
     const int groups = 64 / R;
     const int lane = (int)threadIdx.x;
     const int grp = lane / R, run = lane - grp * R;
@@ -771,8 +782,8 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
     const int tail = lead + R - 1;                    // lane making run R-1
     const uint64_t gmask = R == 64 ? ~0ull : ((1ull << R) - 1);
     LaneGrid<W, 64> g0{smem + lead};
-    const uint32_t count = a.ws.counters[kCntCand + klass];
-    const uint32_t* queue = a.ws.sorted[klass];
+    const uint32_t count = *count_in;
+    const uint32_t* queue = queue_in;
     const uint32_t stride = gridDim.x * (uint32_t)groups;
 
     // static round-robin over the size-sorted queue; the next entry is
@@ -842,7 +853,18 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
         const int last = first < R ? first : R - 1;
         const int incl = wave_inclusive_sum(active && run <= last ? st.steps : 0);
         const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead);
-        const bool det = active && cls == JATAM_DET;
+        // without a witness in a first pass the candidate waits for the second
+        const bool undecided = active && first == R && !all_runs && cls == JATAM_DET;
+        const uint64_t um = __ballot(undecided && run == 0);
+        if (um != 0) {
+            uint32_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(count_out, (uint32_t)__popcll(um));
+            base = (uint32_t)__shfl((int)base, 0);
+            if (undecided && run == 0)
+                queue_out[base + (uint32_t)__popcll(um & lanes_below())] = idx;
+        }
+        const bool det = active && cls == JATAM_DET && !undecided;
         const int size0 = __shfl(st.size, lead);
         // run 0's shape: from the wave's cache, else the group's lanes share
         // its 8 orientation hashes
@@ -866,7 +888,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             }
         }
         wave_lds_sync();
-        const bool done = active && run == 0;
+        const bool done = active && run == 0 && !undecided;
         uint32_t h = 0;
         if (done) {
             jatam_result_t rec;
@@ -1145,6 +1167,26 @@ static void launch_first(const BatchArgs& a, uint32_t nb, hipStream_t stream, in
                            klass);
 }
 
+// The R-lanes-per-candidate repeat kernel of grid class k for one pass.
+template <int TM>
+static void launch_repeat(const BatchArgs& a, int k, bool table, uint32_t rb, int rpass,
+                          const uint32_t* qin, const uint32_t* cin, uint32_t* qout,
+                          uint32_t* cout, hipStream_t stream)
+{
+    if (k == 0 && table)
+        hipLaunchKernelGGL((repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a, 0,
+                           rpass, qin, cin, qout, cout);
+    else if (k == 0)
+        hipLaunchKernelGGL((repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a, 0,
+                           rpass, qin, cin, qout, cout);
+    else if (table)
+        hipLaunchKernelGGL((repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a, 1,
+                           rpass, qin, cin, qout, cout);
+    else
+        hipLaunchKernelGGL((repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a, 1,
+                           rpass, qin, cin, qout, cout);
+}
+
 template <int TM>
 static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch launch[2],
                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
@@ -1225,14 +1267,23 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             else
                 hipLaunchKernelGGL((repeat_seq_kernel<32, TM, false>), dim3(rb), dim3(64), 0,
                                    stream, a, 1);
-        } else if (k == 0 && table)
-            hipLaunchKernelGGL((repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a, 0);
-        else if (k == 0)
-            hipLaunchKernelGGL((repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a, 0);
-        else if (table)
-            hipLaunchKernelGGL((repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a, 1);
-        else
-            hipLaunchKernelGGL((repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a, 1);
+        } else {
+            // one pass of R lanes per candidate, or (mapping 2) a first pass
+            // of kRepeatFirstRuns lanes whose undecided candidates go to the
+            // staging array (free after the compaction) for a second pass
+            const bool two = launch[k].repeat_mapping == 2 && a.runs > kRepeatFirstRuns;
+            const uint32_t* q0 = a.ws.sorted[k];
+            const uint32_t* c0 = a.ws.counters + kCntCand + k;
+            uint32_t* q1 = a.ws.cand_idx[k];
+            uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;
+            if (two) {
+                hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream, c1);
+                launch_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, q0, c0, q1, c1, stream);
+                launch_repeat<TM>(a, k, table, rb, a.runs, q1, c1, nullptr, nullptr, stream);
+            } else {
+                launch_repeat<TM>(a, k, table, rb, a.runs, q0, c0, nullptr, nullptr, stream);
+            }
+        }
         end(kStageRepeat + kStagesPerClass * k);
     }
 }

@@ -23,6 +23,8 @@ struct Params {
 
 int launch_plain(const uint64_t* genomes, uint64_t first, int64_t n, const Params& prm,
                  jatam_result_t* out, hipStream_t stream);
+int launch_variant(const uint64_t* genomes, uint64_t first, int64_t n, const Params& prm,
+                   int variant, jatam_result_t* out, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // Pipelined path.  Grid class 0 = G <= 16 (16 x 16 torus), 1 = G <= 32.
@@ -34,10 +36,12 @@ enum {
     kCntCandAll = 4,  // [2] candidates before the forced-shape proof
     kCntOverflow = 6, // items that left the 16 x 16 window (rerun in 32 x 32 grids)
     kCntClaim = 7,    // [2] chunks claimed past the static share (first-run stage)
+    kCntRepeat2 = 9,  // [2] candidates left for the second repeat pass
     kCntWords = 16,
 };
 constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
 constexpr int kMaxClaimChunks = 8;  // most 64-item chunks one first-run claim may take
+constexpr int kRepeatFirstRuns = 4; // runs per candidate in the first of two repeat passes
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
 constexpr int kMaxScanBlocks = 1024;
 
@@ -107,7 +111,8 @@ struct StageLaunch {
     int repeat_blocks;
     int dyn16;
     int claim_chunks;
-    int repeat_mapping;   // 0: R lanes per candidate; 1: one lane per candidate (W = 16)
+    int repeat_mapping;   // 0: R lanes per candidate; 1: one lane per candidate;
+                          // 2: kRepeatFirstRuns lanes first, R lanes for the undecided
 };
 
 // occ[grid class][TM == 2 ? 0 : 1][0 first runs, 1 repeat runs (R lanes per
@@ -115,7 +120,7 @@ struct StageLaunch {
 // blocks per CU of the stage kernels.
 void batch_occupancy(int occ[2][2][3]);
 // Default launch parameters of a grid class.
-jatam_tuning_t default_tuning();
+jatam_tuning_t default_tuning(int klass);
 // Largest first-run grid (one-wave blocks) over the classes and tile bounds.
 int max_first_blocks(const int occ[2][2][3], int cus);
 // Whether the size scan can cover that many first-run blocks.

@@ -94,7 +94,7 @@ extern "C" int jatam_classify_static(const uint64_t* genotypes, int64_t n, int t
         return sc;
     jatam::BatchArgs a = jatam::batch_args_for(p, n, out, tally, d->ws, d->small_hash);
     a.genomes = genotypes;
-    const jatam_tuning_t tune[2] = {jatam::default_tuning(), jatam::default_tuning()};
+    const jatam_tuning_t tune[2] = {jatam::default_tuning(0), jatam::default_tuning(1)};
     return jatam::launch_tuned(tune, d->occ, d->cus, a, grid_limit, t, (hipStream_t)stream,
                                nullptr, nullptr);
 }

@@ -111,6 +111,10 @@ def lib() -> ctypes.CDLL:
         L.jatam_batch_autotune.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64, vp,
                                            ctypes.POINTER(Tuning), vp]
         L.jatam_batch_autotune.restype = i32
+        L.jatam_batch_autotune_cached.argtypes = [vp, ctypes.c_char_p, u64, i64, i32, i32, i32,
+                                                  i32, u64, vp, ctypes.POINTER(Tuning),
+                                                  ctypes.POINTER(ctypes.c_int), vp]
+        L.jatam_batch_autotune_cached.restype = i32
         L.jatam_batch_autotune_log.argtypes = [vp, i32, ctypes.POINTER(Tuning),
                                                ctypes.POINTER(ctypes.c_double)]
         L.jatam_batch_autotune_log.restype = i32
@@ -122,6 +126,8 @@ def lib() -> ctypes.CDLL:
         L.jatam_classify_static.restype = i32
         L.jatam_batch_enumerate.restype = i32
         L.jatam_shape_histogram.argtypes = [vp, i64, vp, i64, vp, vp]
+        L.jatam_classify_variant.argtypes = [vp, u64, i64, i32, i32, i32, i32, u64, i32, vp, vp]
+        L.jatam_classify_variant.restype = i32
         L.jatam_single_mutants.argtypes = [vp, u64, i64, i32, i32, vp, vp]
         L.jatam_single_mutants.restype = i32
         L.jatam_neighbourhood.argtypes = [vp, vp, i64, i32, i32, vp, vp]
@@ -205,6 +211,26 @@ def classify_range(first: int, n: int, t: int, c: int = 8, grid_limit: int = 16,
     rc = lib().jatam_classify_range(first, n, t, c, grid_limit, runs, seed, rec.data_ptr(),
                                     _stream_handle(stream))
     _check(rc, "jatam_classify_range")
+    return rec
+
+
+VARIANT_C4, VARIANT_LIFO = 1, 2   # jatam_classify_variant flags
+
+
+def classify_variant(genotypes: torch.Tensor | None, t: int, variant: int, c: int = 8,
+                     grid_limit: int = 16, runs: int = 20, seed: int = 1, first: int = 0,
+                     n: int | None = None, out: torch.Tensor | None = None, device="cuda",
+                     stream=None) -> torch.Tensor:
+    """jatam_classify_variant: VARIANT_C4 and/or VARIANT_LIFO; genotypes None
+    means the range first + i."""
+    if genotypes is not None:
+        n = genotypes.shape[0]
+        device = genotypes.device
+    rec = _records(n, device, out)
+    rc = lib().jatam_classify_variant(genotypes.data_ptr() if genotypes is not None else None,
+                                      first, n, t, c, grid_limit, runs, seed, variant,
+                                      rec.data_ptr(), _stream_handle(stream))
+    _check(rc, "jatam_classify_variant")
     return rec
 
 
@@ -723,6 +749,18 @@ class Batch:
             lib().jatam_batch_autotune_log(self._h, i, ctypes.byref(e), ctypes.byref(ms))
             log.append((e.as_dict(), ms.value))
         return best.as_dict(), log
+
+    def autotune_cached(self, path: str, first: int, n: int, t: int, c: int = 8,
+                        grid_limit: int = 16, runs: int = 20, seed: int = 1, stream=None):
+        """jatam_batch_autotune_cached; returns (parameters, from_cache)."""
+        scratch = torch.empty((2 * n, 4), dtype=torch.int32, device="cuda")
+        best, hit = Tuning(), ctypes.c_int(0)
+        rc = lib().jatam_batch_autotune_cached(self._h, os.fsencode(path), first, n, t, c,
+                                               grid_limit, runs, seed, scratch.data_ptr(),
+                                               ctypes.byref(best), ctypes.byref(hit),
+                                               _stream_handle(stream))
+        _check(rc, "jatam_batch_autotune_cached")
+        return best.as_dict(), bool(hit.value)
 
     def ga_step(self, pop: torch.Tensor, fit: torch.Tensor, t: int, params: GAParams,
                 generation: int, c: int = 8, grid_limit: int = 32, runs: int = 20,

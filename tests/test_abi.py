@@ -191,3 +191,18 @@ def test_roulette_rejects_bad_arguments(lib):
                               None) == -1
     assert lib.jatam_fujiyama(ctypes.byref(good), lam, 2, 1, 64, 33, 100, buf, buf, None,
                               None) == -1
+
+
+def test_classify_variant_rejects_bad_arguments(lib):
+    out = ctypes.create_string_buffer(64)
+    assert lib.jatam_classify_variant(None, 0, 1, 2, 8, 16, 20, 1, 4, out, None) == -1
+    assert lib.jatam_classify_variant(None, 0, 1, 0, 8, 16, 20, 1, 1, out, None) == -1
+    assert lib.jatam_classify_variant(None, (1 << 24) - 1, 2, 2, 8, 16, 20, 1, 1, out, None) == -1
+    assert lib.jatam_classify_variant(None, 0, 0, 2, 8, 16, 20, 1, 3, None, None) == 0
+
+
+def test_autotune_cached_rejects_bad_arguments(lib):
+    buf = ctypes.create_string_buffer(64)
+    assert lib.jatam_batch_autotune_cached(None, b"/tmp/x", 0, 1, 2, 8, 16, 20, 1, buf, None,
+                                           None, None) == -1
+    assert "file" in __import__("paper_2205_15311_amd").strerror(-5)

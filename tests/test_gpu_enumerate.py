@@ -125,3 +125,32 @@ def test_window_in_graph_replays(jt):
     keys, counts = np.unique(np.stack([det["size"].astype(np.int64), det["hash"].astype(np.int64)]),
                              axis=1, return_counts=True)
     assert shapes_of(jt, table) == [(int(h), int(z), int(c)) for (z, h), c in zip(keys.T, counts)]
+
+
+def test_s28_resumable_with_a_manifest(jt, tmp_path):
+    """All of S_{2,8} in 16 slices through the manifest driver, stopped after
+    5 slices and resumed: every slice digest and tally is the golden one, as
+    is the total."""
+    import hashlib as hl
+
+    from paper_2205_15311_amd import manifest
+    gold = golden("s28_digests.json")
+    n = gold["slice"]
+    header = {"space": "S_2,8", "t": 2, "c": 8, "grid": 16, "runs": 20, "seed": 1}
+    with jt.Batch(n) as b:
+        def gpu_slice(first, count):
+            rec = b.classify_range(first, count, 2, 8, 16, 20, 1)
+            torch.cuda.synchronize()
+            return rec.cpu().numpy()
+
+        path = str(tmp_path / "s28.jsonl")
+        part = manifest.enumerate_slices(path, header, 0, n, 16, gpu_slice, stop_after=5)
+        assert part["slices_done"] == 5 and not part["complete"]
+        res = manifest.enumerate_slices(path, header, 0, n, 16, gpu_slice)
+    assert res["complete"]
+    entries = [json.loads(x) for x in open(path).read().splitlines()[1:]]
+    for e, s in zip(sorted(entries, key=lambda e: e["slice"]), gold["slices"]):
+        assert e["sha256"] == s["sha256"] and e["tally"] == s["tally"]
+    want = hl.sha256("".join(s["sha256"] for s in gold["slices"]).encode()).hexdigest()
+    assert res["digest"] == want
+    assert res["tally"] == np.sum([s["tally"] for s in gold["slices"]], axis=0).tolist()

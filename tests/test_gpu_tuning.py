@@ -78,6 +78,10 @@ def test_autotune_on_s28_keeps_the_golden_records(jt):
     (16, dict(repeat_mapping=1, repeat_waves=1, wide_layout=1)),
     (32, dict(repeat_mapping=1)),
     (32, dict(repeat_mapping=1, wide_layout=2)),
+    (16, dict(repeat_mapping=2)),
+    (16, dict(repeat_mapping=2, repeat_waves=1, claim_share=0)),
+    (32, dict(repeat_mapping=2)),
+    (32, dict(repeat_mapping=2, wide_layout=2)),
 ])
 def test_explicit_tunings_keep_records(jt, grid, tuning):
     rng = np.random.default_rng(grid + len(tuning))
@@ -110,7 +114,7 @@ def test_bad_tunings_rejected(jt):
         for bad in (dict(refill=0), dict(refill=65), dict(first_waves=0), dict(repeat_waves=0),
                     dict(wide_layout=2), dict(claim_share=-1), dict(claim_share=17),
                     dict(claim_chunks=0), dict(claim_chunks=9), dict(repeat_mapping=-1),
-                    dict(repeat_mapping=2)):
+                    dict(repeat_mapping=3)):
             with pytest.raises(jt.JatamError):
                 b.set_tuning(16, **bad)
         with pytest.raises(jt.JatamError):
@@ -230,16 +234,19 @@ def test_window_and_direct_wide_layout_agree(jt, t, grid):
             assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
 
 
-def test_sequential_repeat_mapping_keeps_the_golden_records(jt):
+@pytest.mark.parametrize("mapping,runs", [(0, 20), (1, 20), (2, 20)])
+def test_repeat_mappings_keep_the_golden_records(jt, mapping, runs):
     """One lane per repeat candidate (runs in turn, stopping at the first
-    witness) over the first 2^22 genotypes of S_{2,8}: the oracle's digests."""
+    witness), and two passes (4 lanes per candidate, then R lanes for the
+    undecided), over the first 2^22 genotypes of S_{2,8}: the oracle's
+    digests."""
     with open(os.path.join(HERE, "golden", "s28_digests.json")) as f:
         gold = json.load(f)
     n = gold["slice"]
     with jt.Batch(4 * n) as b:
-        b.set_tuning(16, repeat_mapping=1)
+        b.set_tuning(16, repeat_mapping=mapping)
         tally = torch.zeros(4, dtype=torch.int64, device="cuda")
-        out = b.classify_range(0, 4 * n, 2, 8, 16, 20, 1, tally=tally)
+        out = b.classify_range(0, 4 * n, 2, 8, 16, runs, 1, tally=tally)
         torch.cuda.synchronize()
         rec = out.cpu().numpy()
     for s in gold["slices"][:4]:
@@ -247,6 +254,22 @@ def test_sequential_repeat_mapping_keeps_the_golden_records(jt):
         assert hashlib.sha256(blob).hexdigest() == s["sha256"], s["first"]
     want = np.sum([s["tally"] for s in gold["slices"][:4]], axis=0).tolist()
     assert tally.cpu().tolist() == want
+
+
+@pytest.mark.parametrize("runs", [1, 2, 4, 5, 7, 33, 64])
+def test_two_pass_repeat_at_every_run_count(jt, runs):
+    """Two repeat passes at run counts below, at and above the first pass's
+    4 runs, on S_{2,8} and three-tile genotypes: the oracle's records."""
+    rng = np.random.default_rng(runs)
+    g2 = rng.integers(0, 1 << 24, size=30_000, dtype=np.uint64)
+    g3 = rng.integers(0, 1 << 36, size=10_000, dtype=np.uint64)
+    with jt.Batch(1 << 15) as b:
+        b.set_tuning(16, repeat_mapping=2)
+        b.set_tuning(32, repeat_mapping=2)
+        got2 = records(b.classify(torch.from_numpy(g2.view(np.int64)).cuda(), 2, 8, 16, runs, 1))
+        got3 = records(b.classify(torch.from_numpy(g3.view(np.int64)).cuda(), 3, 8, 32, runs, 1))
+    assert_same(got2, ref.classify(g2, 2, grid=16, runs=runs, seed=1), f"t=2 R={runs}")
+    assert_same(got3, ref.classify(g3, 3, grid=32, runs=runs, seed=1), f"t=3 R={runs}")
 
 
 def test_classify_batch_with_order_and_call_tuning(jt):
@@ -294,3 +317,27 @@ def test_staging_back_pressure_keeps_records(jt):
                                  tally=tally))
     assert_same(got, want, "all candidates")
     assert tally.cpu().tolist() == [0, 0, 0, len(g)]
+
+
+def test_autotune_cache_file(jt, tmp_path):
+    """The tuning found for a key is written to the cache file and read back
+    instead of searching again; another key adds a line; a broken line of a
+    key is searched again and replaced."""
+    path = tmp_path / "tuning.jsonl"
+    n = 1 << 18
+    with jt.Batch(n) as b:
+        t1, hit1 = b.autotune_cached(str(path), 0, n, 2, 8, 16, 20, 2)
+        assert not hit1
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1 and '"key": "' in lines[0] and "|R20|" in lines[0]
+        b.set_tuning(16, refill=64)
+        t2, hit2 = b.autotune_cached(str(path), 0, n, 2, 8, 16, 20, 2)
+        assert hit2 and t2 == t1 and b.get_tuning(16) == t1
+        _, hit3 = b.autotune_cached(str(path), 0, n, 2, 8, 16, 7, 2)
+        assert not hit3 and len(path.read_text().splitlines()) == 2
+    path.write_text(lines[0].replace('"refill": ', '"refill": x') + "\n")
+    with jt.Batch(n) as b:
+        _, hit4 = b.autotune_cached(str(path), 0, n, 2, 8, 16, 20, 2)
+        assert not hit4
+        fixed = path.read_text().splitlines()
+        assert len(fixed) == 1 and '"refill": x' not in fixed[0]
