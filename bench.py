@@ -268,12 +268,27 @@ def misclass_report(args, jt, torch):
             curve.append({"R": r, "det": int(det.sum()),
                           "misclassified": int((det & ~true_det).sum()),
                           "missed_true_det": int((true_det & ~det).sum())})
+    # the same curve under the paper's own traversal, the LIFO movelist
+    # (plain variant kernel; the true class does not depend on the traversal)
+    curve_lifo = []
+    rec = torch.empty((TOTAL, 4), dtype=torch.int32, device=dev)
+    t1 = time.perf_counter()
+    for r in range(1, 21):
+        jt.classify_variant(None, T, jt.VARIANT_LIFO, runs=r, first=0, n=TOTAL, out=rec,
+                            stream=stream)
+        det = rec[:, 0] == 3
+        curve_lifo.append({"R": r, "det": int(det.sum()),
+                           "misclassified": int((det & ~true_det).sum()),
+                           "missed_true_det": int((true_det & ~det).sum())})
+    lifo_s = time.perf_counter() - t1
     line = {"metric": "S_2,8 genotypes classed DET by R runs that are not truly deterministic "
                       "(G=16, seed 1)",
             "unit": "genotypes", "n_gpus": 1, "genotypes": TOTAL,
             "true_class": dict(counts, cap=cap, seconds=truth_s,
                                genotypes_per_s=TOTAL / truth_s),
             "curve": curve,
+            "curve_lifo": curve_lifo,
+            "lifo_seconds_for_20_runs_counts": lifo_s,
             "data": "exhaustive enumeration of S_2,8"}
     print(json.dumps(line), flush=True)
 

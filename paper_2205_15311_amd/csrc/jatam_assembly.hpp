@@ -774,7 +774,8 @@ __device__ __forceinline__ void bitmap8_dims(uint64_t m, int& w, int& h)
 // window at ymin is cut from the 16 packed rows.  False if the box exceeds
 // 8 x 8.
 template <int B>
-__device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& m)
+__device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& m, int& x0,
+                                                  int& y0)
 {
     uint32_t o[8];
 #pragma unroll
@@ -790,6 +791,8 @@ __device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& 
     cols = (cols | (cols >> 16)) & 0xFFFFu;
     const int ymin = __builtin_ctz(rows), ymax = 31 - __builtin_clz(rows);
     const int xmin = __builtin_ctz(cols), xmax = 31 - __builtin_clz(cols);
+    x0 = xmin;
+    y0 = ymin;
     if (xmax - xmin >= 8 || ymax - ymin >= 8)
         return false;
     uint32_t r[4];
@@ -810,6 +813,13 @@ __device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& 
     return true;
 }
 
+template <int B>
+__device__ __forceinline__ bool shape_bitmap8_w16(LaneGrid<16, B>& g, uint64_t& m)
+{
+    int x0, y0;
+    return shape_bitmap8_w16(g, m, x0, y0);
+}
+
 // The cropped shape as an anchored 8 x 8 bitmap, whatever W.
 template <int W, int B>
 __device__ __forceinline__ bool shape_key8(LaneGrid<W, B>& g, int G, uint64_t& m)
@@ -820,6 +830,130 @@ __device__ __forceinline__ bool shape_key8(LaneGrid<W, B>& g, int G, uint64_t& m
         int w, h;
         return shape_bitmap8(g, G, m, w, h);
     }
+}
+
+// ---------------------------------------------------------------------------
+// A run's final shape packed into 16 bytes, for the proof stage to check
+// without replaying the run: .x/.y the anchored 8 x 8 bitmap (bit 8y + x),
+// .z/.w a 64-bit word holding the tile nibble of every cell in ascending bit
+// order (at most kPackedCells cells) and, in bits 58..63, the seed's bit.
+// All ones in .z/.w: the shape does not fit (larger box or more cells).
+// ---------------------------------------------------------------------------
+constexpr int kPackedCells = 14;
+
+__device__ __forceinline__ bool packed_shape_valid(const uint4& v)
+{
+    return !(v.z == 0xFFFFFFFFu && v.w == 0xFFFFFFFFu);
+}
+
+template <int W, int B>
+__device__ __forceinline__ uint4 pack_shape(LaneGrid<W, B>& g, int G, int size)
+{
+    const uint4 none = make_uint4(0u, 0u, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    if (size > kPackedCells)
+        return none;
+    if constexpr (W == 16) {
+        // the bitmap from the OCC words in registers; then the two PEND words
+        // of each of the box's rows, all reads issued before any is used
+        uint64_t m;
+        int x0, y0;
+        if (!shape_bitmap8_w16(g, m, x0, y0))
+            return none;
+        uint32_t lo[8], hi[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int y = y0 + r < 16 ? y0 + r : 15;
+            lo[r] = g.word(Geometry<16>::kPend + 2 * y);
+            hi[r] = g.word(Geometry<16>::kPend + 2 * y + 1);
+        }
+        uint64_t tiles = 0;
+        int k = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            // the row's 8 nibbles from column x0 on
+            const uint32_t row = (uint32_t)((((uint64_t)hi[r] << 32) | lo[r]) >> (4 * x0));
+            for (uint32_t bits = (uint32_t)(m >> (8 * r)) & 0xFFu; bits != 0;
+                 bits &= bits - 1, ++k) {
+                const int x = __builtin_ctz(bits);
+                tiles |= (uint64_t)((row >> (4 * x)) & 15u) << (4 * k);
+            }
+        }
+        const int sc = G / 2 - 1;
+        tiles |= (uint64_t)((sc - y0) * 8 + (sc - x0)) << 58;
+        return make_uint4((uint32_t)m, (uint32_t)(m >> 32), (uint32_t)tiles,
+                          (uint32_t)(tiles >> 32));
+    }
+    const ShapeBox bx = crop(g, G);
+    if (bx.w > 8 || bx.h > 8)
+        return none;
+    uint64_t m = 0;
+    for (int y = 0; y < bx.h; ++y)
+        m |= (uint64_t)((g.row(bx.ymin + y) >> bx.xmin) & 0xFFu) << (8 * y);
+    uint64_t tiles = 0;
+    int k = 0;
+    for (uint64_t cells = m; cells != 0; cells &= cells - 1, ++k) {
+        const int b = __builtin_ctzll(cells);
+        const int p = (bx.ymin + (b >> 3)) * W + bx.xmin + (b & 7);
+        const uint64_t nib = (g.pend_word(p) >> ((uint32_t)(p & 7) * 4u)) & 15u;
+        tiles |= nib << (4 * k);
+    }
+    const int sc = G / 2 - 1;
+    tiles |= (uint64_t)((sc - bx.ymin) * 8 + (sc - bx.xmin)) << 58;
+    return make_uint4((uint32_t)m, (uint32_t)(m >> 32), (uint32_t)tiles,
+                      (uint32_t)(tiles >> 32));
+}
+
+// shape_is_guarded for a packed shape (same edges, same test), from
+// registers: cell b's tile is nibble popcount(m below b) of the tile word.
+template <class Src>
+__device__ __forceinline__ bool packed_shape_is_guarded(const Src& src, const uint4& v)
+{
+    const uint64_t shape = ((uint64_t)v.y << 32) | v.x;
+    const uint64_t word = ((uint64_t)v.w << 32) | v.z;
+    const uint64_t tiles = word & ((1ull << 56) - 1);
+    const uint64_t seed_bit = 1ull << (int)(word >> 58);
+    uint64_t good0 = 0, good1 = 0, good2 = 0, good3 = 0;
+    uint64_t conf0 = 0, conf1 = 0, conf2 = 0, conf3 = 0;
+    for (uint64_t cells = shape; cells != 0; cells &= cells - 1) {
+        const int b = __builtin_ctzll(cells);
+        const uint64_t bit = 1ull << b;
+        const uint32_t id = (uint32_t)(tiles >> (4 * __popcll(shape & (bit - 1)))) & 15u;
+        const int x = b & 7, y = b >> 3;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const bool inside = d == 0 ? y > 0 : d == 1 ? x < 7 : d == 2 ? y < 7 : x > 0;
+            const int qb = b + (d == 0 ? -8 : d == 1 ? 1 : d == 2 ? 8 : -1);
+            if (!inside || ((shape >> (qb & 63)) & 1ull) == 0ull)
+                continue;
+            const uint32_t nq =
+                (uint32_t)(tiles >> (4 * __popcll(shape & ((1ull << qb) - 1)))) & 15u;
+            // options of the site in direction d + 2 of q's tile: cell b
+            const uint32_t opt = src.options(src.oriented((int)nq), (d + 2) & 3);
+            const bool good = opt != 0 && (opt >> 4) == 1u && (opt & 15u) == id;
+            const bool conf = opt != 0 && !good;
+            const uint64_t gb = good ? bit : 0ull, cb = conf ? bit : 0ull;
+            if (d == 0) { good0 |= gb; conf0 |= cb; }
+            else if (d == 1) { good1 |= gb; conf1 |= cb; }
+            else if (d == 2) { good2 |= gb; conf2 |= cb; }
+            else { good3 |= gb; conf3 |= cb; }
+        }
+    }
+    uint64_t todo = (conf0 | conf1 | conf2 | conf3) & ~seed_bit;
+    bool guarded = true;
+    for (; todo != 0 && guarded; todo &= todo - 1) {
+        const uint64_t pb = todo & (~todo + 1);
+        const uint64_t src_bits = ((conf0 & pb) >> 8) | ((conf2 & pb) << 8) |
+                                  ((conf1 & pb) << 1) | ((conf3 & pb) >> 1);
+        const uint64_t allowed = shape & ~pb;
+        uint64_t reach = seed_bit, prev = 0;
+        while (reach != prev && (reach & src_bits) == 0) {
+            prev = reach;
+            reach |= (((reach << 8) & good0) | ((reach >> 1) & good1) | ((reach >> 8) & good2) |
+                      ((reach << 1) & good3)) & allowed;
+        }
+        guarded = (reach & src_bits) == 0;
+    }
+    return guarded;
 }
 
 // D4 hash of a shape given as an anchored 8 x 8 bitmap, by one lane.

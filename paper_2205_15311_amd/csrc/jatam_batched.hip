@@ -224,6 +224,25 @@ __device__ __forceinline__ uint32_t det_hash(LaneGrid<W, 64>& g, uint32_t small0
     return h;
 }
 
+// D4 hash of a shape given as its anchored 8 x 8 bitmap, for lanes with
+// `want` (called by the whole wave), through the wave's cache.
+__device__ __forceinline__ uint32_t packed_hash(uint64_t key, uint32_t small0, uint32_t small1,
+                                                WaveShapeCache& cache, bool want, int size)
+{
+    uint32_t h = 0;
+    bool miss = false;
+    if (want) {
+        if (size <= 2) {
+            h = size <= 1 ? small0 : small1;
+        } else if (!cache.lookup(key, h)) {
+            h = bitmap8_shape_hash(key);
+            miss = true;
+        }
+    }
+    cache.insert(miss, key, h, lane_id());
+    return h;
+}
+
 // ---------------------------------------------------------------------------
 // first_run<W>: screen + first runs with lane refill.
 // ---------------------------------------------------------------------------
@@ -324,6 +343,8 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 const uint32_t pos = staged + (uint32_t)__popcll(cm & lanes_below());
                 seg_idx[pos] = idx;
                 seg_size[pos] = (uint16_t)st.size;
+                // the shape, for the proof stage to check without a replay
+                a.ws.cand_shape[idx] = pack_shape(g, gd.grid, st.size);
             }
             staged += (uint32_t)__popcll(cm);
         }
@@ -627,19 +648,34 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
         const uint32_t pos = c * 64 + (uint32_t)lane_id();
         const bool active = pos < count;
         uint32_t idx = 0;
-        bool forced = false;
+        bool forced = false, packed = false;
+        int size = 0;
+        uint64_t key = 0;
         Geno gd{0, 0, 0, 0, false};
         if (active) {
             idx = queue[pos];
             gd = run_geno<W>(a, first, idx);
             const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
-            const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
-                                        (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
-            forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
+            const uint4 sh = a.ws.cand_shape[idx];
+            packed = packed_shape_valid(sh);
+            if (packed) {
+                // the first-run stage packed the shape: no replay
+                key = ((uint64_t)sh.y << 32) | sh.x;
+                size = __popcll(key);
+                forced = packed_shape_is_guarded(src, sh);
+            } else {
+                const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
+                                            (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
+                size = st.size;
+                forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
+            }
         }
-        const uint32_t h = det_hash(g, small0, small1, cache, forced, st.size, gd.grid);
+        // hashes: a packed shape's from its bitmap, a replayed one's from the grid
+        uint32_t h = det_hash(g, small0, small1, cache, forced && !packed, size, gd.grid);
+        const uint32_t hp = packed_hash(key, small0, small1, cache, forced && packed, size);
+        h = packed ? hp : h;
         if (forced)
-            out[idx] = jatam_result_t{JATAM_DET, st.size, h, (st.size - 1) * a.runs};
+            out[idx] = jatam_result_t{JATAM_DET, size, h, (size - 1) * a.runs};
         tally.add(forced, JATAM_DET);
         const bool kept = active && !forced;
         if (active)

@@ -60,6 +60,8 @@ struct DeviceWorkspace {
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
     uint32_t* overflow;       // [max_n] items to rerun in 32 x 32 grids
+    uint4* cand_shape;        // [max_n] by genotype index: the packed run-0 shape of
+                              // each DET candidate (pack_shape), for the proof stage
     uint32_t* small_hash;     // [2]: D4 hash of the monomer and of the domino
     jatam_result_t* records;  // [max_n] records of a GA generation
 };

@@ -93,12 +93,29 @@ def test_fujiyama_landscape_adapts():
 
 
 def test_ga_step_fitness_is_det_size():
+    """The generation's fitness is the size of the structure for a
+    deterministic offspring, else 0: checked against the brute-force
+    explorer (its own decoding and from-scratch options) on the offspring
+    whose outcome every growth order fixes (one terminal shape and no event:
+    fitness = its cell count; only events reachable: fitness 0)."""
+    from tests import brute_force as bf
     rng = np.random.default_rng(8)
-    pop = rng.integers(0, 1 << 36, size=2000, dtype=np.uint64)
-    fit = np.zeros(2000, dtype=np.int32)
-    nxt, nfit = ref.ga_step(pop, fit, 3, generation=0, grid=16, runs=20)
-    rec = ref.classify(nxt, 3, grid=16, runs=20)
-    assert np.array_equal(nfit, np.where(rec["cls"] == ref.DET, rec["size"], 0))
+    pop = rng.integers(0, 1 << 24, size=300, dtype=np.uint64)
+    fit = np.zeros(300, dtype=np.int32)
+    nxt, nfit = ref.ga_step(pop, fit, 2, generation=0, grid=16, runs=20)
+    checked = {"det": 0, "nd": 0}
+    for g, f in zip(nxt.tolist(), nfit.tolist()):
+        ex = bf.explore(int(g), 2, 8, 16, cap=800)
+        if ex.capped:
+            continue
+        if ex.truly_det:
+            (shape,) = ex.terminals
+            assert f == len(shape), g
+            checked["det"] += 1
+        elif ex.events and not ex.terminals:
+            assert f == 0, g
+            checked["nd"] += 1
+    assert checked["det"] > 25 and checked["nd"] > 25, checked
 
 
 @pytest.mark.parametrize("bad", [dict(tournament=0), dict(tournament=9), dict(mut=(2, 1)),
