@@ -1293,7 +1293,7 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
     };
     const size_t n = max_n, mb = (size_t)max_blocks;
     // per wave: its share of the chunks, and room for one more claim
-    const size_t staging = n + 64 * (mb * (1 + kMaxClaimChunks) + 1);
+    const size_t staging = staging_entries(n, mb);
     DeviceWorkspace w;
     w.counters = (uint32_t*)take(kCntWords * sizeof(uint32_t));
     w.small_hash = (uint32_t*)take(2 * sizeof(uint32_t));
@@ -1309,7 +1309,8 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
         w.sorted[k] = (uint32_t*)take(n * sizeof(uint32_t));
     }
     w.overflow = (uint32_t*)take(n * sizeof(uint32_t));
-    w.cand_shape = (uint4*)take(n * sizeof(uint4));
+    w.cand_shape = (uint4*)take(staging * sizeof(uint4));
+    w.sorted_shape = (uint4*)take(n * sizeof(uint4));
     if (ws != nullptr)
         *ws = w;
     return at;

@@ -296,6 +296,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     uint32_t staged = 0;                      // candidates in this wave's segment
     uint32_t* seg_idx = a.ws.cand_idx[klass] + (size_t)wave * a.seg_cap;
     uint16_t* seg_size = a.ws.cand_size[klass] + (size_t)wave * a.seg_cap;
+    uint4* seg_shape = a.ws.cand_shape + (size_t)wave * a.seg_cap;
     WaveTally tally{{0, 0, 0, 0}};
 
     bool busy = false;
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 seg_idx[pos] = idx;
                 seg_size[pos] = (uint16_t)st.size;
                 // the shape, for the proof stage to check without a replay
-                a.ws.cand_shape[idx] = pack_shape(g, gd.grid, st.size);
+                seg_shape[pos] = pack_shape(g, gd.grid, st.size);
             }
             staged += (uint32_t)__popcll(cm);
         }
@@ -605,18 +606,22 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
     const uint32_t n = a.ws.seg_count[klass][seg];
     const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
     const uint32_t* ix = a.ws.cand_idx[klass] + (size_t)seg * a.seg_cap;
+    const uint4* sh = a.ws.cand_shape + (size_t)seg * a.seg_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256) {
         const uint32_t pos = atomicAdd(&cursor[size_key(sz[i])], 1u);
         a.ws.sorted[klass][pos] = ix[i];
+        a.ws.sorted_shape[pos] = sh[i];
     }
 }
 
 // ---------------------------------------------------------------------------
-// prove<W>: one lane per candidate (in size order) replays its first run and
-// checks whether the shape is guarded (shape_is_guarded; forced shapes are
-// the case without conflicts): then every run ends in it and the record is
-// final without the repeat runs -- DET, run 0's size and hash, (size - 1) * R
-// placements.  The other candidates are kept,
+// prove<W>: one lane per candidate (in size order) takes its run-0 shape as
+// the first-run stage packed it (the sort moved it beside the candidate), or
+// replays run 0 where it did not fit, and checks whether the shape is guarded
+// (shape_is_guarded; forced shapes are the case without conflicts): then
+// every run ends in it and the record is final without the repeat runs --
+// DET, run 0's size and hash, (size - 1) * R placements.  The other
+// candidates are kept,
 // in queue order, for the repeat runs: keep[pos] holds the candidate or
 // kNoCandidate, and chunk_cnt[c] the kept count of queue chunk c (64
 // positions; every chunk below n/64 is written).
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
             idx = queue[pos];
             gd = run_geno<W>(a, first, idx);
             const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
-            const uint4 sh = a.ws.cand_shape[idx];
+            const uint4 sh = a.ws.sorted_shape[pos];
             packed = packed_shape_valid(sh);
             if (packed) {
                 // the first-run stage packed the shape: no replay
@@ -684,15 +689,13 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
         if (lane_id() == 0)
             chunk_cnt[c] = kc;
     }
+    if (blockIdx.x == 0 && lane_id() == 0) {
+        // the candidate count, kept for the compaction (the scan of the kept
+        // counts overwrites kCntCand); the second repeat pass's counter
+        a.ws.counters[kCntCandAll + klass] = count;
+        a.ws.counters[kCntRepeat2 + klass] = 0;
+    }
     tally.flush(a.tally);
-}
-
-// The candidate count before the proof, kept for the compaction (the scan
-// of the kept counts overwrites kCntCand).
-__global__ void copy_count_kernel(const BatchArgs a, int klass)
-{
-    if (threadIdx.x == 0)
-        a.ws.counters[kCntCandAll + klass] = a.ws.counters[kCntCand + klass];
 }
 
 // Kept candidates to the front of the queue, in order (one wave per chunk).
@@ -1246,8 +1249,13 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         const uint64_t nchunks = (uint64_t)(a.n + 63) / 64;
         a.dyn16 = launch[k].dyn16;
         a.claim_chunks = launch[k].claim_chunks;
-        a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64) +
-                    (a.dyn16 > 0 ? (uint32_t)a.claim_chunks * 64u : 0u);
+        // a wave's segment holds its dealt-out share and one claim (the
+        // first-run kernel's claim size, which is 0 where it makes none)
+        const uint64_t per_wave = nchunks / (16u * (uint64_t)nb);
+        const uint32_t claim = a.dyn16 <= 0 ? 0u
+                               : per_wave < (uint64_t)a.claim_chunks ? (uint32_t)per_wave
+                                                                      : (uint32_t)a.claim_chunks;
+        a.seg_cap = (uint32_t)((nchunks + nb - 1) / nb * 64) + claim * 64u;
         begin(kStageFirst + kStagesPerClass * k);
         if (k == 1 && a.narrow_max > 16) {
             // the 32 x 32 class reruns only the items that left the window
@@ -1281,7 +1289,6 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         else
             hipLaunchKernelGGL((prove_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
         const uint32_t qchunks = (uint32_t)nchunks;
-        hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, stream, a, k);
         exclusive_scan(a.ws.chunk_cnt[k], qchunks, a.ws.chunk_sums[k],
                        a.ws.counters + kCntCand + k, stream);
         hipLaunchKernelGGL(compact_kernel, dim3((qchunks * 64 + 255) / 256), dim3(256), 0, stream,
@@ -1313,7 +1320,7 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             uint32_t* q1 = a.ws.cand_idx[k];
             uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;
             if (two) {
-                hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream, c1);
+                // c1 was cleared by the proof stage
                 launch_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, q0, c0, q1, c1, stream);
                 launch_repeat<TM>(a, k, table, rb, a.runs, q1, c1, nullptr, nullptr, stream);
             } else {

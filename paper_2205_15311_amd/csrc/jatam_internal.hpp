@@ -45,6 +45,16 @@ constexpr int kRepeatFirstRuns = 4; // runs per candidate in the first of two re
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
 constexpr int kMaxScanBlocks = 1024;
 
+// Entries of the candidate staging arrays for calls of up to max_n items on
+// at most max_blocks first-run waves: nb waves of ceil(chunks / nb) dealt-out
+// chunks and one claim each, a claim being at most chunks / (16 nb) chunks
+// (claims are made only where every wave gets at least 16 chunks), so at
+// most 64 (chunks + nb) + 4 chunks <= max_n + max_n / 16 + 64 (max_blocks + 2).
+inline size_t staging_entries(size_t max_n, size_t max_blocks)
+{
+    return max_n + max_n / 16 + 64 * (max_blocks + 2);
+}
+
 // Device memory of a jatam_batch_t, sized for max_n genotypes per call and a
 // persistent grid of at most max_blocks one-wave blocks.
 struct DeviceWorkspace {
@@ -52,16 +62,19 @@ struct DeviceWorkspace {
     uint32_t* seg_count[2];   // [max_blocks] candidates staged by each wave
     uint32_t* seg_hist[2];    // [kSizeBuckets * max_blocks] bucket-major counts
     uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
-    uint32_t* chunk_cnt[2];   // [max_n / 64 + 1] kept candidates per queue chunk
+    uint32_t* chunk_cnt[2];   // [max_n / 64 + 1] kept candidates per queue chunk, and
+                              // ([1]) items per input chunk that left the 16 x 16 window
     uint32_t* chunk_sums[2];  // [max_n / 64 / kScanBlock + 1] block totals of their scan
-    uint32_t* cand_idx[2];    // [max_n + 64 * (max_blocks * (1 + kMaxClaimChunks) + 1)]:
-                              // per-wave segments of the first-run grid, each its
-                              // dealt-out share plus one claim of slack
+    uint32_t* cand_idx[2];    // [staging_entries(max_n, max_blocks)]: per-wave
+                              // segments of the first-run grid, each its dealt-out
+                              // share plus one claim of slack
     uint16_t* cand_size[2];   // same layout: run-0 sizes
     uint32_t* sorted[2];      // [max_n] candidates, largest size first
     uint32_t* overflow;       // [max_n] items to rerun in 32 x 32 grids
-    uint4* cand_shape;        // [max_n] by genotype index: the packed run-0 shape of
-                              // each DET candidate (pack_shape), for the proof stage
+    uint4* cand_shape;        // same layout as cand_idx[k] (both classes in turn): the
+                              // packed run-0 shape of each candidate (pack_shape)
+    uint4* sorted_shape;      // [max_n] the same, in the order of sorted[k], for the
+                              // proof stage
     uint32_t* small_hash;     // [2]: D4 hash of the monomer and of the domino
     jatam_result_t* records;  // [max_n] records of a GA generation
 };
