@@ -112,13 +112,14 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
                                            uint32_t* added = nullptr)
 {
     constexpr int kMask = W * W - 1;
-    uint32_t opt[4], ow[4], fw[4], pw[4];
+    uint32_t ow[4], fw[4], pw[4];
+    SiteOpts opt[4];
     int q[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
         q[d] = (p + delta) & kMask;
-        opt[d] = m.options(tuple, d);
+        opt[d] = m.options_split(tuple, d);
     }
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -135,16 +136,18 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
     for (int d = 0; d < 4; ++d) {
         const bool ring = d == 0 ? py == 0 : d == 1 ? px == G - 2 : d == 2 ? py == G - 2 : px == 0;
         const uint32_t bit = (uint32_t)q[d] & 31u;
-        const bool has = opt[d] != 0;
+        const bool has = opt[d].has;
         const bool free = ((ow[d] >> bit) & 1u) == 0;
         const bool live = has && !ring && free;
-        const uint32_t id = opt[d] & 15u;
-        const bool multi = (opt[d] >> 4) >= 2;
+        const uint32_t id = opt[d].id;
+        const bool multi = opt[d].multi;
         const bool in_f = ((fw[d] >> bit) & 1u) != 0;
         const uint32_t sh = ((uint32_t)q[d] & 7u) * 4u;
         const uint32_t pending = (pw[d] >> sh) & 15u;
-        unbound = unbound || (has && ring);
-        ambiguous = ambiguous || (live && (multi || (in_f && pending != id)));
+        // plain (not short-circuit) logic: every operand is at hand, and
+        // lane masks combine with scalar instructions
+        unbound = unbound | (has & ring);
+        ambiguous = ambiguous | (live & (multi | (in_f & (pending != id))));
         if (live && !multi && !in_f) {
             LaneGrid<W, B>::set_bits(g.fr(q[d] >> 5), 1u << bit);
             LaneGrid<W, B>::set_bits(g.pend_word(q[d]), id << sh);
@@ -509,8 +512,8 @@ __device__ __forceinline__ bool shape_is_forced(const Src& m, LaneGrid<W, B>& g,
                     continue;
                 const uint32_t nq = (g.pend_word(q) >> ((uint32_t)(q & 7) * 4u)) & 15u;
                 // options of the site in direction d + 2 of q's tile: cell p
-                const uint32_t opt = m.options(m.oriented((int)nq), (d + 2) & 3);
-                if (opt != 0 && ((opt >> 4) >= 2u || (opt & 15u) != id))
+                const SiteOpts o = m.options_split(m.oriented((int)nq), (d + 2) & 3);
+                if (o.has && (o.multi || o.id != id))
                     forced = false;
             }
         }
@@ -589,9 +592,9 @@ __device__ __forceinline__ bool shape_is_guarded(const Src& m, LaneGrid<W, B>& g
                     continue;
                 const uint32_t nq = (g.pend_word(q) >> ((uint32_t)(q & 7) * 4u)) & 15u;
                 // options of the site in direction d + 2 of q's tile: cell p
-                const uint32_t opt = m.options(m.oriented((int)nq), (d + 2) & 3);
-                const bool good = opt != 0 && (opt >> 4) == 1u && (opt & 15u) == id;
-                const bool conf = opt != 0 && !good;
+                const SiteOpts o = m.options_split(m.oriented((int)nq), (d + 2) & 3);
+                const bool good = o.has & !o.multi & (o.id == id);
+                const bool conf = o.has & !good;
                 const uint64_t gb = good ? bit : 0ull, cb = conf ? bit : 0ull;
                 if (d == 0) { good0 |= gb; conf0 |= cb; }
                 else if (d == 1) { good1 |= gb; conf1 |= cb; }
@@ -928,9 +931,9 @@ __device__ __forceinline__ bool packed_shape_is_guarded(const Src& src, const ui
             const uint32_t nq =
                 (uint32_t)(tiles >> (4 * __popcll(shape & ((1ull << qb) - 1)))) & 15u;
             // options of the site in direction d + 2 of q's tile: cell b
-            const uint32_t opt = src.options(src.oriented((int)nq), (d + 2) & 3);
-            const bool good = opt != 0 && (opt >> 4) == 1u && (opt & 15u) == id;
-            const bool conf = opt != 0 && !good;
+            const SiteOpts o = src.options_split(src.oriented((int)nq), (d + 2) & 3);
+            const bool good = o.has & !o.multi & (o.id == id);
+            const bool conf = o.has & !good;
             const uint64_t gb = good ? bit : 0ull, cb = conf ? bit : 0ull;
             if (d == 0) { good0 |= gb; conf0 |= cb; }
             else if (d == 1) { good1 |= gb; conf1 |= cb; }

@@ -222,8 +222,11 @@ __device__ __forceinline__ Word nibble_splat(uint32_t k)
 // min(count, 2) in bits 4..5 and the lowest representative id in bits 0..3
 // (0 when nothing bonds).  No branches: a colour without a partner masks
 // the match instead.
+// The representatives behind site_options: bit 4k+3 of the result is set
+// for each representative k that bonds.
 template <int TM>
-__device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tuple, int d)
+__device__ __forceinline__ typename Model<TM>::Word site_match(const Model<TM>& m, uint32_t tuple,
+                                                               int d)
 {
     using M = Model<TM>;
     using Word = typename M::Word;
@@ -234,7 +237,38 @@ __device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tu
     const Word v = m.side_col((d + 2) & 3) ^ nibble_splat<Word>((uint32_t)p & 15u);
     // high bit of each nibble set iff the nibble is nonzero (no carries escape)
     const Word nonzero = v | ((v & M::kLow3) + M::kLow3);
-    const Word match = bonds ? (~nonzero & m.reps) : (Word)0;
+    return bonds ? (~nonzero & m.reps) : (Word)0;
+}
+
+// site_options as its three parts, without packing them into a code: any
+// representative bonds, two or more do, the lowest one's id (meaningless
+// when none does).
+struct SiteOpts {
+    bool has, multi;
+    uint32_t id;
+};
+
+template <int TM>
+__device__ __forceinline__ SiteOpts site_options_split(const Model<TM>& m, uint32_t tuple, int d)
+{
+    const typename Model<TM>::Word match = site_match(m, tuple, d);
+    SiteOpts o;
+    o.has = match != 0;
+    o.multi = (match & (match - 1)) != 0;
+    // the top bit is representative 4 TM - 1's: or-ing it in changes no
+    // lowest set bit and keeps the count of trailing zeros defined
+    if constexpr (TM == 2)
+        o.id = (uint32_t)__builtin_ctz((uint32_t)match | 0x80000000u) >> 2;
+    else
+        o.id = (uint32_t)__builtin_ctzll((uint64_t)match | (1ull << 63)) >> 2;
+    return o;
+}
+
+template <int TM>
+__device__ __forceinline__ uint32_t site_options(const Model<TM>& m, uint32_t tuple, int d)
+{
+    using Word = typename Model<TM>::Word;
+    const Word match = site_match(m, tuple, d);
     const Word lowest = match != 0 ? match : (Word)1;   // ctz of 0 is undefined
     uint32_t id;
     if constexpr (TM == 2)
@@ -259,6 +293,10 @@ struct ModelSource {
     {
         return site_options(m, tuple, d);
     }
+    __device__ __forceinline__ SiteOpts options_split(uint32_t tuple, int d) const
+    {
+        return site_options_split(m, tuple, d);
+    }
     __device__ __forceinline__ uint32_t seed() const { return seed_tile(m); }
     __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
 };
@@ -277,6 +315,11 @@ struct TableSource {
     {
         const uint32_t x = (tuple >> (4 * d)) & 7u;
         return (uint32_t)(side[d] >> (8u * x)) & 0x3Fu;
+    }
+    __device__ __forceinline__ SiteOpts options_split(uint32_t tuple, int d) const
+    {
+        const uint32_t code = options(tuple, d);
+        return SiteOpts{code != 0, (code >> 4) >= 2, code & 15u};
     }
     __device__ __forceinline__ uint32_t seed() const { return seed_tile(m); }
     __device__ __forceinline__ uint32_t oriented(int k) const { return oriented_tile(m, k); }
