@@ -546,16 +546,20 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 }
 
 // In-place exclusive scan of h[0..total) in blocks of kScanBlock; block b's
-// total goes to sums[b].
+// total goes to sums[b].  With `items` given, only the first
+// ceil(*items / 64) entries (the chunks of *items queue positions) are read
+// and scanned; the rest count as zero.
 __global__ __launch_bounds__(kScanBlock) void scan_blocks_kernel(uint32_t* h, uint32_t total,
-                                                                 uint32_t* sums)
+                                                                 uint32_t* sums,
+                                                                 const uint32_t* items)
 {
     __shared__ uint32_t wsum[kScanBlock / 64 + 1];
+    const uint32_t n = items != nullptr ? min(total, (*items + 63u) / 64u) : total;
     const uint32_t i = blockIdx.x * kScanBlock + threadIdx.x;
-    const uint32_t v = i < total ? h[i] : 0u;
+    const uint32_t v = i < n ? h[i] : 0u;
     uint32_t sum;
     const uint32_t excl = block_exclusive_scan(v, wsum, &sum);
-    if (i < total)
+    if (i < n)
         h[i] = excl;
     if (threadIdx.x == 0)
         sums[blockIdx.x] = sum;
@@ -584,11 +588,11 @@ __global__ __launch_bounds__(kScanBlock) void scan_sums_kernel(uint32_t* sums, u
 }
 
 static void exclusive_scan(uint32_t* h, uint32_t total, uint32_t* sums, uint32_t* total_out,
-                           hipStream_t stream)
+                           hipStream_t stream, const uint32_t* items = nullptr)
 {
     const uint32_t blocks = (total + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(scan_blocks_kernel, dim3(blocks), dim3(kScanBlock), 0, stream, h, total,
-                       sums);
+                       sums, items);
     hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, stream, sums, blocks,
                        total_out);
 }
@@ -624,7 +628,8 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
 // candidates are kept,
 // in queue order, for the repeat runs: keep[pos] holds the candidate or
 // kNoCandidate, and chunk_cnt[c] the kept count of queue chunk c (64
-// positions; every chunk below n/64 is written).
+// positions; every chunk that holds a candidate is written, and the scan
+// and the compaction read no other).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kNoCandidate = 0xFFFFFFFFu;
 
@@ -648,8 +653,8 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
     const uint32_t* queue = a.ws.sorted[klass];
     uint32_t* keep = a.ws.cand_idx[klass];
     uint32_t* chunk_cnt = a.ws.chunk_cnt[klass];
-    const uint32_t nchunks = (uint32_t)((a.n + 63) / 64);
-    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint32_t qchunks = (count + 63) / 64;   // queue chunks holding candidates
+    for (uint32_t c = blockIdx.x; c < qchunks; c += gridDim.x) {
         const uint32_t pos = c * 64 + (uint32_t)lane_id();
         const bool active = pos < count;
         uint32_t idx = 0;
@@ -701,18 +706,18 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
 // Kept candidates to the front of the queue, in order (one wave per chunk).
 __global__ __launch_bounds__(256) void compact_kernel(const BatchArgs a, int klass)
 {
-    const uint32_t count_all = (uint32_t)((a.n + 63) / 64) * 64;
-    const uint32_t pos = blockIdx.x * 256 + threadIdx.x;
-    if (pos >= count_all)
-        return;
-    const uint32_t c = pos >> 6;
-    const bool in_queue = pos < a.ws.counters[kCntCandAll + klass];
-    const uint32_t v = in_queue ? a.ws.cand_idx[klass][pos] : kNoCandidate;
-    const bool kept = v != kNoCandidate;
-    const uint64_t m = __ballot(kept);
-    if (kept) {
-        const uint32_t base = a.ws.chunk_cnt[klass][c] + a.ws.chunk_sums[klass][c / kScanBlock];
-        a.ws.sorted[klass][base + (uint32_t)__popcll(m & lanes_below())] = v;
+    const uint32_t count = a.ws.counters[kCntCandAll + klass];
+    const uint32_t span = (count + 63) / 64 * 64;   // whole chunks: every wave ballots
+    for (uint32_t pos = blockIdx.x * 256 + threadIdx.x; pos < span; pos += gridDim.x * 256) {
+        const uint32_t c = pos >> 6;
+        const uint32_t v = pos < count ? a.ws.cand_idx[klass][pos] : kNoCandidate;
+        const bool kept = v != kNoCandidate;
+        const uint64_t m = __ballot(kept);
+        if (kept) {
+            const uint32_t base =
+                a.ws.chunk_cnt[klass][c] + a.ws.chunk_sums[klass][c / kScanBlock];
+            a.ws.sorted[klass][base + (uint32_t)__popcll(m & lanes_below())] = v;
+        }
     }
 }
 
@@ -1290,9 +1295,10 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             hipLaunchKernelGGL((prove_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
         const uint32_t qchunks = (uint32_t)nchunks;
         exclusive_scan(a.ws.chunk_cnt[k], qchunks, a.ws.chunk_sums[k],
-                       a.ws.counters + kCntCand + k, stream);
-        hipLaunchKernelGGL(compact_kernel, dim3((qchunks * 64 + 255) / 256), dim3(256), 0, stream,
-                           a, k);
+                       a.ws.counters + kCntCand + k, stream, a.ws.counters + kCntCandAll + k);
+        // a grid-stride loop over the candidates' chunks only (the count is
+        // on the device)
+        hipLaunchKernelGGL(compact_kernel, dim3(nb), dim3(256), 0, stream, a, k);
         end(kStageProve + kStagesPerClass * k);
         begin(kStageRepeat + kStagesPerClass * k);
         // the bond table holds colours 0..7
