@@ -794,11 +794,24 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
 // With rpass < R (the first of two passes) a group of rpass lanes makes runs
 // 0 .. rpass-1 of its candidate: a witness among them decides the record as
 // above; a candidate without one goes to queue_out (count_out counts them)
-// for the second pass, rpass = R, which makes all of its runs.  Most
+// for the second pass, rpass = R, which makes the rest of its runs.  Most
 // non-deterministic candidates are decided by run 1, 2 or 3, so the first
 // pass spares most of the runs a single pass would make.
+//
+// A candidate left undecided by runs 0 .. k-1 ended all of them in run 0's
+// occupancy, with size0 - 1 placements each.  In the 16 x 16 layout the
+// first pass stores that occupancy (8 words, at the candidate's queue_out
+// position of the occupancy store `occ`), and the second pass (skip = k)
+// then makes runs k .. R-1 only, each compared with the stored words.
+__device__ __forceinline__ uint32_t* occ_word(uint4* lo, uint4* hi, uint32_t slot, int w)
+{
+    // words 0..3 of a slot in lo[slot], words 4..7 in hi[slot]
+    return w < 4 ? (uint32_t*)&lo[slot] + w : (uint32_t*)&hi[slot] + (w - 4);
+}
+
 template <int W, int TM, bool kTable>
 __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass, int rpass,
+                                                    int skip, bool store_occ,
                                                     const uint32_t* queue_in,
                                                     const uint32_t* count_in,
                                                     uint32_t* queue_out, uint32_t* count_out)
@@ -817,13 +830,15 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
     RunState st{0, 0, 0, 0, 0, false};
     WaveTally tally{{0, 0, 0, 0}};
 
-    const int R = rpass;                              // runs made in this pass
+    // runs skip .. rpass-1 of each candidate in this pass, one per lane
+    const int R = rpass - skip;
     const bool all_runs = rpass >= a.runs;
     const int groups = 64 / R;
     const int lane = (int)threadIdx.x;
-    const int grp = lane / R, run = lane - grp * R;
-    const int lead = grp * R;                         // lane making run 0
-    const int tail = lead + R - 1;                    // lane making run R-1
+    const int grp = lane / R, jr = lane - grp * R;
+    const int run = skip + jr;
+    const int lead = grp * R;                         // lane making run `skip`
+    const int tail = lead + R - 1;                    // lane making run rpass-1
     const uint64_t gmask = R == 64 ? ~0ull : ((1ull << R) - 1);
     LaneGrid<W, 64> g0{smem + lead};
     const uint32_t count = *count_in;
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             if (active) {
                 gd = run_geno<W>(a, first, idx);
                 src.m = build_model<TM>(gd.genome, gd.t, a.bits, a.c);
-                for (int j = run; j < 8; j += R)
+                for (int j = jr; j < 8; j += R)
                     orient[j][grp] = bond_table_word(src.m, j);
             }
             wave_lds_sync();
@@ -870,14 +885,29 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             }
         }
         wave_lds_sync();   // every run's grid is final (and the table slots read)
-        // a witness is a later run that hit an event or ended in another shape
+        // a witness is a later run that hit an event or ended in another
+        // shape than run 0 (the lead lane's, or the stored one)
         bool same = true;
-        if (active && run > 0 && ev == kEvNone) {
+        int stored_size = 0;                          // run 0's size, from the store
+        if constexpr (W == 16) {
+            if (skip > 0 && active) {
+                const uint32_t slot = base + (uint32_t)grp;
+                uint4* const lo = a.ws.sorted_shape;
+                uint4* const hi = a.ws.cand_shape;
+#pragma unroll
+                for (int w = 0; w < Geo::kWords; ++w) {
+                    const uint32_t o = *occ_word(lo, hi, slot, w);
+                    stored_size += __popc(o);
+                    same = same && g.occ(w) == o;
+                }
+            }
+        }
+        if (skip == 0 && active && jr > 0 && ev == kEvNone) {
 #pragma unroll
             for (int w = 0; w < Geo::kWords; ++w)
                 same = same && g.occ(w) == g0.occ(w);
         }
-        const bool witness = active && run > 0 && (ev != kEvNone || !same);
+        const bool witness = active && (skip > 0 || jr > 0) && (ev != kEvNone || !same);
         const uint64_t wm = (__ballot(witness) >> lead) & gmask;
         const int first = wm ? (int)__builtin_ctzll(wm) : R;      // R: no witness
         const int wl = lead + (first < R ? first : 0);
@@ -893,20 +923,32 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
             cls = w_ev == kEvUnbound ? JATAM_UNBOUND
                 : w_ev == kEvAmbig   ? JATAM_ND_SITE
                                      : JATAM_ND_RUNS;
-        // placements summed over runs 0..first (all R runs if DET)
+        // placements summed over runs 0..first (all R runs if DET); the
+        // skipped runs made size0 - 1 each
         const int last = first < R ? first : R - 1;
-        const int incl = wave_inclusive_sum(active && run <= last ? st.steps : 0);
-        const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead);
+        const int incl = wave_inclusive_sum(active && jr <= last ? st.steps : 0);
+        const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead) +
+                          skip * (__shfl(stored_size, lead) - 1);
         // without a witness in a first pass the candidate waits for the second
         const bool undecided = active && first == R && !all_runs && cls == JATAM_DET;
-        const uint64_t um = __ballot(undecided && run == 0);
+        const uint64_t um = __ballot(undecided && jr == 0);
         if (um != 0) {
-            uint32_t base = 0;
+            uint32_t at = 0;
             if (lane == 0)
-                base = atomicAdd(count_out, (uint32_t)__popcll(um));
-            base = (uint32_t)__shfl((int)base, 0);
-            if (undecided && run == 0)
-                queue_out[base + (uint32_t)__popcll(um & lanes_below())] = idx;
+                at = atomicAdd(count_out, (uint32_t)__popcll(um));
+            at = (uint32_t)__shfl((int)at, 0);
+            const uint32_t slot = at + (uint32_t)__popcll(um & lanes_below());
+            if (undecided && jr == 0)
+                queue_out[slot] = idx;
+            if constexpr (W == 16) {
+                // every run of the group ended in run 0's occupancy: lane jr
+                // stores words jr, jr + R, ... of its own
+                const uint32_t gslot = (uint32_t)__shfl((int)slot, lead);
+                if (store_occ && undecided) {
+                    for (int w = jr; w < Geo::kWords; w += R)
+                        *occ_word(a.ws.sorted_shape, a.ws.cand_shape, gslot, w) = g.occ(w);
+                }
+            }
         }
         const bool det = active && cls == JATAM_DET && !undecided;
         const int size0 = __shfl(st.size, lead);
@@ -922,17 +964,17 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
                 if (small) {
                     int w8, h8;
                     bitmap8_dims(key, w8, h8);
-                    for (int k = run; k < 8; k += R)
+                    for (int k = jr; k < 8; k += R)
                         orient[k][grp] = bitmap_hash8(image8(key, w8, h8, k));
                 } else {
                     const ShapeBox bx = crop(g0, gd.grid);
-                    for (int k = run; k < 8; k += R)
+                    for (int k = jr; k < 8; k += R)
                         orient[k][grp] = orientation_hash(g0, bx, k);
                 }
             }
         }
         wave_lds_sync();
-        const bool done = active && run == 0 && !undecided;
+        const bool done = active && jr == 0 && !undecided;
         uint32_t h = 0;
         if (done) {
             jatam_result_t rec;
@@ -1214,21 +1256,21 @@ static void launch_first(const BatchArgs& a, uint32_t nb, hipStream_t stream, in
 // The R-lanes-per-candidate repeat kernel of grid class k for one pass.
 template <int TM>
 static void launch_repeat(const BatchArgs& a, int k, bool table, uint32_t rb, int rpass,
-                          const uint32_t* qin, const uint32_t* cin, uint32_t* qout,
-                          uint32_t* cout, hipStream_t stream)
+                          int skip, bool store_occ, const uint32_t* qin, const uint32_t* cin,
+                          uint32_t* qout, uint32_t* cout, hipStream_t stream)
 {
     if (k == 0 && table)
         hipLaunchKernelGGL((repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a, 0,
-                           rpass, qin, cin, qout, cout);
+                           rpass, skip, store_occ, qin, cin, qout, cout);
     else if (k == 0)
         hipLaunchKernelGGL((repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a, 0,
-                           rpass, qin, cin, qout, cout);
+                           rpass, skip, store_occ, qin, cin, qout, cout);
     else if (table)
         hipLaunchKernelGGL((repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a, 1,
-                           rpass, qin, cin, qout, cout);
+                           rpass, 0, false, qin, cin, qout, cout);
     else
         hipLaunchKernelGGL((repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a, 1,
-                           rpass, qin, cin, qout, cout);
+                           rpass, 0, false, qin, cin, qout, cout);
 }
 
 template <int TM>
@@ -1327,10 +1369,17 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;
             if (two) {
                 // c1 was cleared by the proof stage
-                launch_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, q0, c0, q1, c1, stream);
-                launch_repeat<TM>(a, k, table, rb, a.runs, q1, c1, nullptr, nullptr, stream);
+                // in the 16 x 16 layout the first pass stores the undecided
+                // candidates' run-0 occupancy and the second makes only runs
+                // kRepeatFirstRuns .. R-1 (the 32 x 32 layout remakes them all)
+                const int skip = k == 0 ? kRepeatFirstRuns : 0;
+                launch_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, 0, k == 0, q0, c0, q1, c1,
+                                  stream);
+                launch_repeat<TM>(a, k, table, rb, a.runs, skip, false, q1, c1, nullptr, nullptr,
+                                  stream);
             } else {
-                launch_repeat<TM>(a, k, table, rb, a.runs, q0, c0, nullptr, nullptr, stream);
+                launch_repeat<TM>(a, k, table, rb, a.runs, 0, false, q0, c0, nullptr, nullptr,
+                                  stream);
             }
         }
         end(kStageRepeat + kStagesPerClass * k);
