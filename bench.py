@@ -27,6 +27,7 @@ alone (for profiles); `--no-autotune` keeps the default launch parameters.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -84,15 +85,31 @@ KERNEL_SOURCES = ("jatam_batched.hip", "jatam_assembly.hpp", "jatam_device.hpp",
                   "jatam_internal.hpp")
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    summary (copy-calibrated), or None once the kernel sources differ from
-    the ones the counters were taken on."""
+def code_text(src):
+    """C++ source without its comments and with runs of white space made one
+    blank: what the compiler sees, so that editing a comment does not count
+    as changing a kernel.  (The kernel sources hold no string literal with
+    comment markers in it.)"""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_sources_digest():
+    """First 16 hex digits of the sha256 of the kernel sources' code text
+    (code_text of each file in KERNEL_SOURCES, joined by newlines)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2205_15311_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    digest = h.hexdigest()[:16]
+        with open(os.path.join(ROOT, "paper_2205_15311_amd", "csrc", name)) as f:
+            h.update((code_text(f.read()) + "\n").encode())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (copy-calibrated), or None once the kernel code differs from the
+    code the counters were taken on (kernel_sources_digest)."""
+    digest = kernel_sources_digest()
     try:
         with open(COUNTER_PROFILE) as f:
             lines = f.read().splitlines()

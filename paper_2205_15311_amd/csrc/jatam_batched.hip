@@ -18,28 +18,32 @@
 //                 differ.  A first run ending in an event or without ever
 //                 drawing a random word is final; one that drew and ended
 //                 cleanly makes the genotype a DET candidate, staged with its
-//                 size in the wave's own segment.
+//                 size and its packed run-0 shape in the wave's own segment.
 //   size sort     a counting sort of the candidates by run-0 size, largest
 //                 first (all runs of a deterministic genotype have that size,
-//                 so this orders the repeat work by its exact cost): per
+//                 so this orders the later work by its exact cost): per
 //                 segment histograms in LDS, one scan, scatter with LDS
-//                 cursors.
-//   prove<W>      one lane per candidate replays run 0 and checks whether its
-//                 shape is guarded (every growth order ends in it): then the
+//                 cursors that moves each packed shape beside its candidate.
+//   prove<W>      one lane per candidate checks whether its run-0 shape is
+//                 guarded (every growth order ends in it), from the packed
+//                 shape or, where the shape did not pack, a replay: then the
 //                 record is final; the other candidates are compacted.
 //   repeat<W>     R lanes per candidate, lane r making run r; the first
 //                 witness in run order (an event or a shape different from
 //                 run 0's) is found in LDS, and for DET genotypes the 8
-//                 orientation hashes are split across the group's lanes.  Or
-//                 (repeat_seq) one lane per candidate making its runs in
-//                 turn and stopping at the first witness.
+//                 orientation hashes are split across the group's lanes.
+//                 By default in two passes (runs 0-3, then the rest for the
+//                 candidates without a witness).  Or (repeat_seq) one lane per
+//                 candidate making its runs in turn and stopping at the first
+//                 witness.
 //
-// The only global atomic on a shared counter is the first-run claim counter,
+// Global atomics on shared counters are rare: the first-run claim counter,
 // taken a few chunks at a time by waves that have finished their dealt-out
-// share (same-address atomics serialise across the 8 XCDs, so claims are
-// rare); every other queue is a per-wave segment or a scan.  Records are
-// identical to the plain kernel's: each is a pure function of the genotype,
-// never of the schedule.
+// share (same-address atomics serialise across the 8 XCDs), and the second
+// repeat queue's counter, one atomic per wave and round of the first pass;
+// every other queue is a per-wave segment or a scan.  Records are identical
+// to the plain kernel's: each is a pure function of the genotype, never of
+// the schedule.
 #include "jatam_assembly.hpp"
 #include "jatam_internal.hpp"
 
@@ -703,7 +707,8 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
     tally.flush(a.tally);
 }
 
-// Kept candidates to the front of the queue, in order (one wave per chunk).
+// Kept candidates to the front of the queue, in order: a grid-stride loop
+// over the queue chunks that hold candidates, a wave per chunk at a time.
 __global__ __launch_bounds__(256) void compact_kernel(const BatchArgs a, int klass)
 {
     const uint32_t count = a.ws.counters[kCntCandAll + klass];
