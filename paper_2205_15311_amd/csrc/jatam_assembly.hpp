@@ -92,7 +92,24 @@ struct RunState {
     int size;
     int steps;
     bool choice;
+    // 32 x 32 layout: frontier sites per group of four rows, 16-bit fields,
+    // groups 0-3 in gca and 4-7 in gcb (the frontier select's first level)
+    uint64_t gca = 0, gcb = 0;
 };
+
+// 32 x 32 layout: the frontier count of cell q's group of four rows goes up
+// (add) or down by one.  Nothing in the 16 x 16 layout.
+template <int W>
+__device__ __forceinline__ void frontier_group_add(RunState& st, int q, bool add)
+{
+    if constexpr (W == 32) {
+        const int grp = q >> 7;
+        const uint64_t one = 1ull << (16 * (grp & 3));
+        const uint64_t d = add ? one : 0ull - one;
+        st.gca += grp < 4 ? d : 0ull;
+        st.gcb += grp < 4 ? 0ull : d;
+    }
+}
 
 // The tile `tuple` was just placed at p: check its empty neighbours (§3.2).
 // A bondable site on the ring means the structure leaves the box; a site
@@ -153,6 +170,7 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
             LaneGrid<W, B>::set_bits(g.pend_word(q[d]), id << sh);
             st.fsum |= 1u << (q[d] >> 5);
             st.nf += 1;
+            frontier_group_add<W>(st, q[d], true);
             if (added != nullptr)
                 *added |= 1u << d;
         }
@@ -300,6 +318,8 @@ __device__ __forceinline__ int run_clear(LaneGrid<W, B>& g, RunState& st, Draws&
     }
     st.nf = 0;
     st.fsum = 0;
+    st.gca = 0;
+    st.gcb = 0;
     st.size = 1;
     st.steps = 0;
     st.choice = false;
@@ -349,6 +369,7 @@ __device__ __forceinline__ int run_start_known(LaneGrid<W, B>& g, RunState& st, 
             LaneGrid<W, B>::set_bits(g.pend_word(q), (opt & 15u) << sh);
             st.fsum |= 1u << (q >> 5);
             st.nf += 1;
+            frontier_group_add<W>(st, q, true);
         }
     }
     return unbound ? kEvUnbound : ambiguous ? kEvAmbig : kEvNone;
@@ -405,47 +426,39 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
         j -= b2 ? ecd : eab;
         w = (int)wi;
     } else {
-        // the nonzero frontier words four at a time: four independent LDS
-        // reads per round instead of one round trip per word
-        uint32_t fs = st.fsum;
-        bool found = false;
-        while (fs != 0 && !found) {
-            const uint32_t s1 = fs & (fs - 1), s2 = s1 & (s1 - 1), s3 = s2 & (s2 - 1);
-            const int w0 = __builtin_ctz(fs);
-            const int w1 = s1 ? __builtin_ctz(s1) : w0;
-            const int w2 = s2 ? __builtin_ctz(s2) : w0;
-            const int w3 = s3 ? __builtin_ctz(s3) : w0;
-            const uint32_t f0 = g.fr(w0);
-            const uint32_t f1 = s1 ? g.fr(w1) : 0u;
-            const uint32_t f2 = s2 ? g.fr(w2) : 0u;
-            const uint32_t f3 = s3 ? g.fr(w3) : 0u;
-            const uint32_t c0 = __popc(f0), c1 = __popc(f1), c2 = __popc(f2), c3 = __popc(f3);
-            if (j < c0) {
-                w = w0;
-                fw = f0;
-                found = true;
-            } else if (j < c0 + c1) {
-                w = w1;
-                fw = f1;
-                j -= c0;
-                found = true;
-            } else if (j < c0 + c1 + c2) {
-                w = w2;
-                fw = f2;
-                j -= c0 + c1;
-                found = true;
-            } else if (j < c0 + c1 + c2 + c3) {
-                w = w3;
-                fw = f3;
-                j -= c0 + c1 + c2;
-                found = true;
-            } else {
-                j -= c0 + c1 + c2 + c3;
-                fs = s3 & (s3 - 1);
-            }
-        }
-        if (!found)
-            return kEvCorrupt;   // nf disagrees with the bitmap: cannot happen
+        // two levels, one round of LDS reads: the frontier counts of the 8
+        // groups of four rows (registers, 16-bit fields) pick the group, its
+        // four words the row.  Inclusive prefix sums of the group counts:
+        uint64_t pa = st.gca;
+        pa += pa << 16;
+        pa += pa << 32;
+        uint64_t pb = st.gcb;
+        pb += pb << 16;
+        pb += pb << 32;
+        pb += (pa >> 48) * 0x0001000100010001ull;   // groups 4-7 follow groups 0-3
+        if ((uint32_t)(pb >> 48) != st.nf)
+            return kEvCorrupt;   // the counts disagree with nf: cannot happen
+        // the group holding site j is the number of prefixes <= j: a field
+        // p (< 2^15, as j + 1 is) has bit 15 of (p | 2^15) - (j + 1) set
+        // exactly when p > j, with no borrow between fields
+        constexpr uint64_t kHigh = 0x8000800080008000ull;
+        const uint64_t jj = (uint64_t)(j + 1u) * 0x0001000100010001ull;
+        const uint32_t grp = 8u - (uint32_t)__popcll(((pa | kHigh) - jj) & kHigh) -
+                             (uint32_t)__popcll(((pb | kHigh) - jj) & kHigh);
+        const uint32_t gm = (grp - 1u) & 7u;   // the group before, if any
+        const uint64_t below = gm < 4u ? pa : pb;
+        j -= grp == 0u ? 0u : (uint32_t)(below >> (16u * (gm & 3u))) & 0xFFFFu;
+        const int w0 = (int)grp * 4;
+        const uint32_t f0 = g.fr(w0), f1 = g.fr(w0 + 1), f2 = g.fr(w0 + 2), f3 = g.fr(w0 + 3);
+        const uint32_t c0 = __popc(f0), c1 = c0 + __popc(f1), c2 = c1 + __popc(f2);
+        const uint32_t j1 = j + 1u;
+        const uint32_t wi = ((c0 - j1) >> 31) + ((c1 - j1) >> 31) + ((c2 - j1) >> 31);
+        const bool b0 = (wi & 1u) != 0, b1 = (wi & 2u) != 0;
+        fw = b1 ? (b0 ? f3 : f2) : (b0 ? f1 : f0);
+        j -= b1 ? (b0 ? c2 : c1) : (b0 ? c0 : 0u);
+        w = w0 + (int)wi;
+        if (j >= (uint32_t)__popc(fw))
+            return kEvCorrupt;   // the counts disagree with the bitmap: cannot happen
     }
     // the j-th set bit of the word: j is below the word's frontier count,
     // nearly always 0..2, so clearing the lowest bit j times beats a
@@ -460,6 +473,7 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
     if (fw == 0)
         st.fsum &= ~(1u << w);
     st.nf -= 1;
+    frontier_group_add<W>(st, p, false);
 
     // place the pending tile (its nibble stays: the cell keeps its tile)
     const uint32_t pw = g.pend_word(p);
