@@ -81,6 +81,29 @@ def test_random_genotypes(jt, t, grid):
     assert_same(got, ref.classify(gs, t, grid=grid, runs=20, seed=1), f"t={t} G={grid}")
 
 
+@pytest.mark.parametrize("grid", [18, 22, 26, 30])
+def test_wide_layout_long_runs(jt, grid):
+    """Grids of 17 < G < 32 run in the 32 x 32 layout, whose frontier select
+    keeps per-group counts of four rows: genotypes whose runs place many
+    tiles (UNBOUND runs that fill the box, large DET shapes) put frontier
+    sites in every group and across group edges.  The sample is the
+    three-tile genotypes of a seeded draw whose oracle record has at least
+    40 placements, plus as many ordinary ones."""
+    rng = np.random.default_rng(4100 + grid)
+    gs = rng.integers(0, 1 << 36, size=40_000, dtype=np.uint64)
+    want = ref.classify(gs, 3, grid=grid, runs=20, seed=1)
+    long = np.nonzero(want["steps"] >= 40)[0][:3000]
+    assert len(long) >= 200, f"only {len(long)} long runs at G={grid}"
+    pick = np.concatenate([long, np.arange(len(long))])
+    sub = np.ascontiguousarray(gs[pick])
+    dev = torch.from_numpy(sub.view(np.int64)).cuda()
+    got = gpu_records(jt.classify(dev, 3, 8, grid, 20, 1))
+    assert_same(got, want[pick], f"plain G={grid}")
+    with jt.Batch(len(sub)) as b:
+        got = gpu_records(b.classify(dev, 3, 8, grid, 20, 1))
+    assert_same(got, want[pick], f"batched G={grid}")
+
+
 @pytest.mark.parametrize("runs,seed", [(1, 1), (7, 123456789), (64, (1 << 63) + 5)])
 def test_runs_and_seeds(jt, runs, seed):
     rng = np.random.default_rng(runs)
