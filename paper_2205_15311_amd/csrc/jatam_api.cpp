@@ -1311,6 +1311,7 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
     w.overflow = (uint32_t*)take(n * sizeof(uint32_t));
     w.cand_shape = (uint4*)take(staging * sizeof(uint4));
     w.sorted_shape = (uint4*)take(n * sizeof(uint4));
+    w.occ_hi = (uint4*)take(n * sizeof(uint4));
     if (ws != nullptr)
         *ws = w;
     return at;

@@ -503,6 +503,8 @@ __global__ __launch_bounds__(256) void sort_hist_kernel(BatchArgs a, int klass)
     if (threadIdx.x < kSizeBuckets)
         hist[threadIdx.x] = 0;
     __syncthreads();
+    if (seg == 0 && threadIdx.x == 0)
+        a.ws.counters[kCntRepeat2 + klass] = 0;   // the second repeat queue, empty
     const uint32_t n = a.ws.seg_count[klass][seg];
     const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256)
@@ -637,10 +639,52 @@ __global__ __launch_bounds__(256) void sort_scatter_kernel(BatchArgs a, int klas
 // ---------------------------------------------------------------------------
 constexpr uint32_t kNoCandidate = 0xFFFFFFFFu;
 
+// The proof of the candidate at queue position pos of the size-sorted queue
+// (lanes with `active`): a guarded shape gets its record here; otherwise
+// the candidate is kept (the return value) for the repeat runs.  Called by
+// the whole wave.
+template <int W, int TM>
+__device__ __forceinline__ bool prove_one(const BatchArgs& a, uint64_t first,
+                                          jatam_result_t* out, LaneGrid<W, 64>& g, RunState& st,
+                                          WaveShapeCache& cache, WaveTally& tally, int klass,
+                                          bool active, uint32_t pos, uint32_t& idx)
+{
+    bool forced = false, packed = false;
+    int size = 0;
+    uint64_t key = 0;
+    Geno gd{0, 0, 0, 0, false};
+    idx = 0;
+    if (active) {
+        idx = a.ws.sorted[klass][pos];
+        gd = run_geno<W>(a, first, idx);
+        const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
+        const uint4 sh = a.ws.sorted_shape[pos];
+        packed = packed_shape_valid(sh);
+        if (packed) {
+            // the first-run stage packed the shape: no replay
+            key = ((uint64_t)sh.y << 32) | sh.x;
+            size = __popcll(key);
+            forced = packed_shape_is_guarded(src, sh);
+        } else {
+            const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
+                                        (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
+            size = st.size;
+            forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
+        }
+    }
+    // hashes: a packed shape's from its bitmap, a replayed one's from the grid
+    uint32_t h = det_hash(g, a.small0, a.small1, cache, forced && !packed, size, gd.grid);
+    const uint32_t hp = packed_hash(key, a.small0, a.small1, cache, forced && packed, size);
+    h = packed ? hp : h;
+    if (forced)
+        out[idx] = jatam_result_t{JATAM_DET, size, h, (size - 1) * a.runs};
+    tally.add(forced, JATAM_DET);
+    return active && !forced;
+}
+
 template <int W, int TM>
 __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
 {
-    const uint32_t small0 = a.small0, small1 = a.small1;
     using Geo = Geometry<W>;
     const uint64_t first = slice_first(a);
     jatam_result_t* const out = slice_out(a);
@@ -654,44 +698,15 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
     RunState st{0, 0, 0, 0, 0, false};
     WaveTally tally{{0, 0, 0, 0}};
     const uint32_t count = a.ws.counters[kCntCand + klass];
-    const uint32_t* queue = a.ws.sorted[klass];
     uint32_t* keep = a.ws.cand_idx[klass];
     uint32_t* chunk_cnt = a.ws.chunk_cnt[klass];
     const uint32_t qchunks = (count + 63) / 64;   // queue chunks holding candidates
     for (uint32_t c = blockIdx.x; c < qchunks; c += gridDim.x) {
         const uint32_t pos = c * 64 + (uint32_t)lane_id();
         const bool active = pos < count;
-        uint32_t idx = 0;
-        bool forced = false, packed = false;
-        int size = 0;
-        uint64_t key = 0;
-        Geno gd{0, 0, 0, 0, false};
-        if (active) {
-            idx = queue[pos];
-            gd = run_geno<W>(a, first, idx);
-            const ModelSource<TM> src{build_model<TM>(gd.genome, gd.t, a.bits, a.c)};
-            const uint4 sh = a.ws.sorted_shape[pos];
-            packed = packed_shape_valid(sh);
-            if (packed) {
-                // the first-run stage packed the shape: no replay
-                key = ((uint64_t)sh.y << 32) | sh.x;
-                size = __popcll(key);
-                forced = packed_shape_is_guarded(src, sh);
-            } else {
-                const int ev = run_assembly(src, g, st, gd.grid, 0, a.key0, a.key1,
-                                            (uint32_t)gd.rng_id, (uint32_t)(gd.rng_id >> 32));
-                size = st.size;
-                forced = ev == kEvNone && shape_is_guarded(src, g, st, gd.grid);
-            }
-        }
-        // hashes: a packed shape's from its bitmap, a replayed one's from the grid
-        uint32_t h = det_hash(g, small0, small1, cache, forced && !packed, size, gd.grid);
-        const uint32_t hp = packed_hash(key, small0, small1, cache, forced && packed, size);
-        h = packed ? hp : h;
-        if (forced)
-            out[idx] = jatam_result_t{JATAM_DET, size, h, (size - 1) * a.runs};
-        tally.add(forced, JATAM_DET);
-        const bool kept = active && !forced;
+        uint32_t idx;
+        const bool kept =
+            prove_one<W, TM>(a, first, out, g, st, cache, tally, klass, active, pos, idx);
         if (active)
             keep[pos] = kept ? idx : kNoCandidate;
         const uint32_t kc = (uint32_t)__popcll(__ballot(kept));
@@ -700,9 +715,8 @@ __global__ __launch_bounds__(64) void prove_kernel(const BatchArgs a, int klass)
     }
     if (blockIdx.x == 0 && lane_id() == 0) {
         // the candidate count, kept for the compaction (the scan of the kept
-        // counts overwrites kCntCand); the second repeat pass's counter
+        // counts overwrites kCntCand)
         a.ws.counters[kCntCandAll + klass] = count;
-        a.ws.counters[kCntRepeat2 + klass] = 0;
     }
     tally.flush(a.tally);
 }
@@ -805,62 +819,62 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
 //
 // A candidate left undecided by runs 0 .. k-1 ended all of them in run 0's
 // occupancy, with size0 - 1 placements each.  In the 16 x 16 layout the
-// first pass stores that occupancy (8 words, at the candidate's queue_out
-// position of the occupancy store `occ`), and the second pass (skip = k)
-// then makes runs k .. R-1 only, each compared with the stored words.
+// first pass stores that occupancy (8 words at the candidate's queue_out
+// position: words 0-3 in cand_shape, free after the size sort, 4-7 in
+// occ_hi), and the second pass (skip = k) then makes runs k .. R-1 only,
+// each compared with the stored words.
 __device__ __forceinline__ uint32_t* occ_word(uint4* lo, uint4* hi, uint32_t slot, int w)
 {
     // words 0..3 of a slot in lo[slot], words 4..7 in hi[slot]
     return w < 4 ? (uint32_t*)&lo[slot] + w : (uint32_t*)&hi[slot] + (w - 4);
 }
 
+// The LDS and the per-lane layout of the R-lanes-per-candidate repeat runs:
+// runs skip .. rpass-1 of each candidate, lane jr of group grp making run
+// skip + jr.  round() runs one candidate per group (active groups only) to
+// its record, or (a first pass without a witness) to the second queue.
 template <int W, int TM, bool kTable>
-__global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass, int rpass,
-                                                    int skip, bool store_occ,
-                                                    const uint32_t* queue_in,
-                                                    const uint32_t* count_in,
-                                                    uint32_t* queue_out, uint32_t* count_out)
-{
+struct RepeatWave {
     using Geo = Geometry<W>;
-    const uint64_t first = slice_first(a);
-    jatam_result_t* const out = slice_out(a);
-    __shared__ uint32_t smem[Geo::kLaneWords * 64];
-    __shared__ uint32_t orient[8][64];   // per group: the 8 orientation hashes
-    __shared__ uint4 cache_mem[kShapeCache];
-    LaneGrid<W, 64> g{smem + threadIdx.x};
-    g.clear_all();
-    WaveShapeCache cache{cache_mem};
-    cache.clear(lane_id());
-    __syncthreads();
-    RunState st{0, 0, 0, 0, 0, false};
-    WaveTally tally{{0, 0, 0, 0}};
+    const BatchArgs& a;
+    uint64_t first;
+    jatam_result_t* out;
+    LaneGrid<W, 64> g;       // this lane's grid
+    LaneGrid<W, 64> g0;      // the group's lead lane's grid
+    uint32_t (*orient)[64];  // per group: bond table words, then orientation hashes
+    WaveShapeCache& cache;
+    RunState& st;
+    WaveTally& tally;
+    int skip;
+    bool store_occ, all_runs;
+    int R, groups, lane, grp, jr, run, lead, tail;
+    uint64_t gmask;
+    uint32_t* queue_out;
+    uint32_t* count_out;
 
-    // runs skip .. rpass-1 of each candidate in this pass, one per lane
-    const int R = rpass - skip;
-    const bool all_runs = rpass >= a.runs;
-    const int groups = 64 / R;
-    const int lane = (int)threadIdx.x;
-    const int grp = lane / R, jr = lane - grp * R;
-    const int run = skip + jr;
-    const int lead = grp * R;                         // lane making run `skip`
-    const int tail = lead + R - 1;                    // lane making run rpass-1
-    const uint64_t gmask = R == 64 ? ~0ull : ((1ull << R) - 1);
-    LaneGrid<W, 64> g0{smem + lead};
-    const uint32_t count = *count_in;
-    const uint32_t* queue = queue_in;
-    const uint32_t stride = gridDim.x * (uint32_t)groups;
+    __device__ RepeatWave(const BatchArgs& a_, uint32_t* smem, uint32_t (*orient_)[64],
+                          WaveShapeCache& cache_, RunState& st_, WaveTally& tally_, int rpass,
+                          int skip_, bool store_occ_, uint32_t* queue_out_, uint32_t* count_out_)
+        : a(a_), first(slice_first(a_)), out(slice_out(a_)), g{smem + threadIdx.x},
+          g0{smem}, orient(orient_), cache(cache_), st(st_), tally(tally_), skip(skip_),
+          store_occ(store_occ_), all_runs(rpass >= a_.runs), R(rpass - skip_),
+          groups(64 / (rpass - skip_)), lane((int)threadIdx.x), grp(0), jr(0), run(0), lead(0),
+          tail(0), gmask(0), queue_out(queue_out_), count_out(count_out_)
+    {
+        grp = lane / R;
+        jr = lane - grp * R;
+        run = skip + jr;
+        lead = grp * R;            // lane making run `skip`
+        tail = lead + R - 1;       // lane making run rpass-1
+        gmask = R == 64 ? ~0ull : ((1ull << R) - 1);
+        g0 = LaneGrid<W, 64>{smem + lead};
+    }
 
-    // static round-robin over the size-sorted queue; the next entry is
-    // fetched one iteration ahead
-    uint32_t base = blockIdx.x * (uint32_t)groups;
-    uint32_t next_idx = 0;
-    if (grp < groups && base + (uint32_t)grp < count)
-        next_idx = queue[base + grp];
-    for (; base < count; base += stride) {
-        const bool active = grp < groups && base + (uint32_t)grp < count;
-        const uint32_t idx = next_idx;
-        if (grp < groups && base + stride + (uint32_t)grp < count)
-            next_idx = queue[base + stride + grp];
+    // `active`: this lane's group has candidate idx (wave-uniform per group);
+    // `slot`: its position in the input queue (where a first pass stored
+    // run 0's occupancy, read when skip > 0).  Called by the whole wave.
+    __device__ void round(bool active, uint32_t idx, uint32_t slot)
+    {
         Geno gd{0, 0, 0, 0, false};
         int ev = kEvNone;
         if constexpr (kTable) {
@@ -896,9 +910,8 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
         int stored_size = 0;                          // run 0's size, from the store
         if constexpr (W == 16) {
             if (skip > 0 && active) {
-                const uint32_t slot = base + (uint32_t)grp;
-                uint4* const lo = a.ws.sorted_shape;
-                uint4* const hi = a.ws.cand_shape;
+                uint4* const lo = a.ws.cand_shape;
+                uint4* const hi = a.ws.occ_hi;
 #pragma unroll
                 for (int w = 0; w < Geo::kWords; ++w) {
                     const uint32_t o = *occ_word(lo, hi, slot, w);
@@ -914,44 +927,44 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
         }
         const bool witness = active && (skip > 0 || jr > 0) && (ev != kEvNone || !same);
         const uint64_t wm = (__ballot(witness) >> lead) & gmask;
-        const int first = wm ? (int)__builtin_ctzll(wm) : R;      // R: no witness
-        const int wl = lead + (first < R ? first : 0);
+        const int fw = wm ? (int)__builtin_ctzll(wm) : R;      // R: no witness
+        const int wl = lead + (fw < R ? fw : 0);
         const int w_ev = __shfl(ev, wl);
         const int w_size = __shfl(st.size, wl);
         const int lead_ev = __shfl(ev, lead);
         int cls;
-        if (lead_ev == kEvCorrupt || (first < R && w_ev == kEvCorrupt))
+        if (lead_ev == kEvCorrupt || (fw < R && w_ev == kEvCorrupt))
             cls = JATAM_INVALID;
-        else if (first == R)
+        else if (fw == R)
             cls = JATAM_DET;
         else
             cls = w_ev == kEvUnbound ? JATAM_UNBOUND
                 : w_ev == kEvAmbig   ? JATAM_ND_SITE
                                      : JATAM_ND_RUNS;
-        // placements summed over runs 0..first (all R runs if DET); the
-        // skipped runs made size0 - 1 each
-        const int last = first < R ? first : R - 1;
+        // placements summed over runs 0..first witness (all R runs if DET);
+        // the skipped runs made size0 - 1 each
+        const int last = fw < R ? fw : R - 1;
         const int incl = wave_inclusive_sum(active && jr <= last ? st.steps : 0);
         const int steps = __shfl(incl, tail) - __shfl(incl, lead) + __shfl(st.steps, lead) +
                           skip * (__shfl(stored_size, lead) - 1);
         // without a witness in a first pass the candidate waits for the second
-        const bool undecided = active && first == R && !all_runs && cls == JATAM_DET;
+        const bool undecided = active && fw == R && !all_runs && cls == JATAM_DET;
         const uint64_t um = __ballot(undecided && jr == 0);
         if (um != 0) {
             uint32_t at = 0;
             if (lane == 0)
                 at = atomicAdd(count_out, (uint32_t)__popcll(um));
             at = (uint32_t)__shfl((int)at, 0);
-            const uint32_t slot = at + (uint32_t)__popcll(um & lanes_below());
+            const uint32_t qslot = at + (uint32_t)__popcll(um & lanes_below());
             if (undecided && jr == 0)
-                queue_out[slot] = idx;
+                queue_out[qslot] = idx;
             if constexpr (W == 16) {
                 // every run of the group ended in run 0's occupancy: lane jr
                 // stores words jr, jr + R, ... of its own
-                const uint32_t gslot = (uint32_t)__shfl((int)slot, lead);
+                const uint32_t gslot = (uint32_t)__shfl((int)qslot, lead);
                 if (store_occ && undecided) {
                     for (int w = jr; w < Geo::kWords; w += R)
-                        *occ_word(a.ws.sorted_shape, a.ws.cand_shape, gslot, w) = g.occ(w);
+                        *occ_word(a.ws.cand_shape, a.ws.occ_hi, gslot, w) = g.occ(w);
                 }
             }
         }
@@ -1007,6 +1020,110 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
         cache.insert(done && det && small && !hit, key, h, lane);
         wave_lds_sync();   // orientation slots and grids reused next round
     }
+};
+
+template <int W, int TM, bool kTable>
+__global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass, int rpass,
+                                                    int skip, bool store_occ,
+                                                    const uint32_t* queue_in,
+                                                    const uint32_t* count_in,
+                                                    uint32_t* queue_out, uint32_t* count_out)
+{
+    using Geo = Geometry<W>;
+    __shared__ uint32_t smem[Geo::kLaneWords * 64];
+    __shared__ uint32_t orient[8][64];
+    __shared__ uint4 cache_mem[kShapeCache];
+    LaneGrid<W, 64> lg{smem + threadIdx.x};
+    lg.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
+    RunState st{0, 0, 0, 0, 0, false};
+    WaveTally tally{{0, 0, 0, 0}};
+    RepeatWave<W, TM, kTable> rw(a, smem, orient, cache, st, tally, rpass, skip, store_occ,
+                                 queue_out, count_out);
+    const uint32_t count = *count_in;
+    const uint32_t groups = (uint32_t)rw.groups, grp = (uint32_t)rw.grp;
+    const uint32_t stride = gridDim.x * groups;
+
+    // static round-robin over the size-sorted queue; the next entry is
+    // fetched one iteration ahead
+    uint32_t base = blockIdx.x * groups;
+    uint32_t next_idx = 0;
+    if (grp < groups && base + grp < count)
+        next_idx = queue_in[base + grp];
+    for (; base < count; base += stride) {
+        const bool active = grp < groups && base + grp < count;
+        const uint32_t idx = next_idx;
+        if (grp < groups && base + stride + grp < count)
+            next_idx = queue_in[base + stride + grp];
+        rw.round(active, idx, base + grp);
+    }
+    tally.flush(a.tally);
+}
+
+// ---------------------------------------------------------------------------
+// prove_repeat<W>: the proof and the first repeat pass in one kernel.  A
+// wave proves 64 positions of the size-sorted queue at a time (prove_one)
+// and keeps its unproven candidates in LDS; whenever they fill its repeat
+// groups (64 / rpass of them) it makes their runs 0 .. rpass-1
+// (RepeatWave::round).  The proof's steady integer work and the runs'
+// latency-bound steps share the CUs, and no compaction or launch sits
+// between them.  With rpass < R the candidates without a witness go to the
+// second queue (count_out, cleared by the size sort), in the 16 x 16 layout
+// with run 0's occupancy stored.
+// ---------------------------------------------------------------------------
+template <int W, int TM, bool kTable>
+__global__ __launch_bounds__(64) void prove_repeat_kernel(const BatchArgs a, int klass,
+                                                          int rpass, uint32_t* queue_out,
+                                                          uint32_t* count_out)
+{
+    using Geo = Geometry<W>;
+    __shared__ uint32_t smem[Geo::kLaneWords * 64];
+    __shared__ uint32_t orient[8][64];
+    __shared__ uint4 cache_mem[kShapeCache];
+    __shared__ uint32_t pend[128];   // unproven candidates waiting for a round
+    LaneGrid<W, 64> lg{smem + threadIdx.x};
+    lg.clear_all();
+    WaveShapeCache cache{cache_mem};
+    cache.clear(lane_id());
+    __syncthreads();
+    RunState st{0, 0, 0, 0, 0, false};
+    WaveTally tally{{0, 0, 0, 0}};
+    RepeatWave<W, TM, kTable> rw(a, smem, orient, cache, st, tally, rpass, 0, W == 16,
+                                 queue_out, count_out);
+    const uint32_t count = a.ws.counters[kCntCand + klass];
+    const uint32_t qchunks = (count + 63) / 64;
+    const uint32_t groups = (uint32_t)rw.groups, grp = (uint32_t)rw.grp;
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t npend = 0;   // wave-uniform, below groups between chunks
+    // one round on the first k waiting candidates, the rest moved down
+    auto round_of = [&](uint32_t k) {
+        const uint32_t pidx = grp < k ? pend[grp] : 0u;
+        rw.round(grp < k, pidx, 0u);
+        const uint32_t rest = npend - k;   // < 64
+        const uint32_t v = lane < rest ? pend[k + lane] : 0u;
+        wave_lds_sync();
+        if (lane < rest)
+            pend[lane] = v;
+        wave_lds_sync();
+        npend = rest;
+    };
+    for (uint32_t c = blockIdx.x; c < qchunks; c += gridDim.x) {
+        const uint32_t pos = c * 64 + lane;
+        uint32_t idx;
+        const bool kept = prove_one<W, TM>(a, rw.first, rw.out, lg, st, cache, tally, klass,
+                                           pos < count, pos, idx);
+        const uint64_t km = __ballot(kept);
+        if (kept)
+            pend[npend + (uint32_t)__popcll(km & lanes_below())] = idx;
+        npend += (uint32_t)__popcll(km);
+        wave_lds_sync();
+        while (npend >= groups)
+            round_of(groups);
+    }
+    while (npend > 0)
+        round_of(npend < groups ? npend : groups);
     tally.flush(a.tally);
 }
 
@@ -1191,10 +1308,17 @@ static void occupancy_of(int out[3])
             hipSuccess ||
         out[0] < 1)
         out[0] = 1;
+    // the repeat grid runs the proof + first pass kernel and the second pass
+    int fused = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[1], repeat_kernel<W, TM, true>, 64, 0) !=
             hipSuccess ||
         out[1] < 1)
         out[1] = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fused, prove_repeat_kernel<W, TM, true>, 64,
+                                                     0) != hipSuccess ||
+        fused < 1)
+        fused = 1;
+    out[1] = out[1] < fused ? out[1] : fused;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[2], repeat_seq_kernel<W, TM, true>, 64,
                                                      0) != hipSuccess ||
         out[2] < 1)
@@ -1278,6 +1402,25 @@ static void launch_repeat(const BatchArgs& a, int k, bool table, uint32_t rb, in
                            rpass, 0, false, qin, cin, qout, cout);
 }
 
+// The proof + first repeat pass kernel of grid class k.
+template <int TM>
+static void launch_prove_repeat(const BatchArgs& a, int k, bool table, uint32_t rb, int rpass,
+                                uint32_t* qout, uint32_t* cout, hipStream_t stream)
+{
+    if (k == 0 && table)
+        hipLaunchKernelGGL((prove_repeat_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream, a,
+                           0, rpass, qout, cout);
+    else if (k == 0)
+        hipLaunchKernelGGL((prove_repeat_kernel<16, TM, false>), dim3(rb), dim3(64), 0, stream, a,
+                           0, rpass, qout, cout);
+    else if (table)
+        hipLaunchKernelGGL((prove_repeat_kernel<32, TM, true>), dim3(rb), dim3(64), 0, stream, a,
+                           1, rpass, qout, cout);
+    else
+        hipLaunchKernelGGL((prove_repeat_kernel<32, TM, false>), dim3(rb), dim3(64), 0, stream, a,
+                           1, rpass, qout, cout);
+}
+
 template <int TM>
 static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch launch[2],
                           hipStream_t stream, hipEvent_t* marks, uint8_t* launched)
@@ -1334,23 +1477,42 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
                        a.ws.counters + kCntCand + k, stream);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nb), dim3(256), 0, stream, a, k);
         end(kStageSort + kStagesPerClass * k);
-        // forced shapes are final; the rest are compacted for the repeat runs
-        begin(kStageProve + kStagesPerClass * k);
-        if (k == 0)
-            hipLaunchKernelGGL((prove_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
-        else
-            hipLaunchKernelGGL((prove_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
-        const uint32_t qchunks = (uint32_t)nchunks;
-        exclusive_scan(a.ws.chunk_cnt[k], qchunks, a.ws.chunk_sums[k],
-                       a.ws.counters + kCntCand + k, stream, a.ws.counters + kCntCandAll + k);
-        // a grid-stride loop over the candidates' chunks only (the count is
-        // on the device)
-        hipLaunchKernelGGL(compact_kernel, dim3(nb), dim3(256), 0, stream, a, k);
-        end(kStageProve + kStagesPerClass * k);
-        begin(kStageRepeat + kStagesPerClass * k);
         // the bond table holds colours 0..7
         const bool table = a.c <= 8;
-        if (launch[k].repeat_mapping == 1) {
+        if (launch[k].repeat_mapping != 1) {
+            // the proof and the first (mapping 2) or only (mapping 0) repeat
+            // pass in one kernel on the repeat grid; with two passes the
+            // undecided candidates go to the staging array (free after the
+            // sort) for the second, which in the 16 x 16 layout makes only
+            // runs kRepeatFirstRuns .. R-1 (the 32 x 32 layout remakes all)
+            const bool two = launch[k].repeat_mapping == 2 && a.runs > kRepeatFirstRuns;
+            uint32_t* q1 = a.ws.cand_idx[k];
+            uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;   // cleared by the size sort
+            begin(kStageProve + kStagesPerClass * k);
+            launch_prove_repeat<TM>(a, k, table, rb, two ? kRepeatFirstRuns : a.runs, q1, c1,
+                                    stream);
+            end(kStageProve + kStagesPerClass * k);
+            begin(kStageRepeat + kStagesPerClass * k);
+            if (two)
+                launch_repeat<TM>(a, k, table, rb, a.runs, k == 0 ? kRepeatFirstRuns : 0, false,
+                                  q1, c1, nullptr, nullptr, stream);
+            end(kStageRepeat + kStagesPerClass * k);
+        } else {
+            // forced shapes are final; the rest are compacted for the
+            // one-lane-per-candidate repeat runs
+            begin(kStageProve + kStagesPerClass * k);
+            if (k == 0)
+                hipLaunchKernelGGL((prove_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
+            else
+                hipLaunchKernelGGL((prove_kernel<32, TM>), dim3(nb), dim3(64), 0, stream, a, 1);
+            const uint32_t qchunks = (uint32_t)nchunks;
+            exclusive_scan(a.ws.chunk_cnt[k], qchunks, a.ws.chunk_sums[k],
+                           a.ws.counters + kCntCand + k, stream, a.ws.counters + kCntCandAll + k);
+            // a grid-stride loop over the candidates' chunks only (the count
+            // is on the device)
+            hipLaunchKernelGGL(compact_kernel, dim3(nb), dim3(256), 0, stream, a, k);
+            end(kStageProve + kStagesPerClass * k);
+            begin(kStageRepeat + kStagesPerClass * k);
             if (k == 0 && table)
                 hipLaunchKernelGGL((repeat_seq_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream,
                                    a, 0);
@@ -1363,31 +1525,8 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             else
                 hipLaunchKernelGGL((repeat_seq_kernel<32, TM, false>), dim3(rb), dim3(64), 0,
                                    stream, a, 1);
-        } else {
-            // one pass of R lanes per candidate, or (mapping 2) a first pass
-            // of kRepeatFirstRuns lanes whose undecided candidates go to the
-            // staging array (free after the compaction) for a second pass
-            const bool two = launch[k].repeat_mapping == 2 && a.runs > kRepeatFirstRuns;
-            const uint32_t* q0 = a.ws.sorted[k];
-            const uint32_t* c0 = a.ws.counters + kCntCand + k;
-            uint32_t* q1 = a.ws.cand_idx[k];
-            uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;
-            if (two) {
-                // c1 was cleared by the proof stage
-                // in the 16 x 16 layout the first pass stores the undecided
-                // candidates' run-0 occupancy and the second makes only runs
-                // kRepeatFirstRuns .. R-1 (the 32 x 32 layout remakes them all)
-                const int skip = k == 0 ? kRepeatFirstRuns : 0;
-                launch_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, 0, k == 0, q0, c0, q1, c1,
-                                  stream);
-                launch_repeat<TM>(a, k, table, rb, a.runs, skip, false, q1, c1, nullptr, nullptr,
-                                  stream);
-            } else {
-                launch_repeat<TM>(a, k, table, rb, a.runs, 0, false, q0, c0, nullptr, nullptr,
-                                  stream);
-            }
+            end(kStageRepeat + kStagesPerClass * k);
         }
-        end(kStageRepeat + kStagesPerClass * k);
     }
 }
 

@@ -75,6 +75,9 @@ struct DeviceWorkspace {
                               // packed run-0 shape of each candidate (pack_shape)
     uint4* sorted_shape;      // [max_n] the same, in the order of sorted[k], for the
                               // proof stage
+    uint4* occ_hi;            // [max_n] words 4-7 of the run-0 occupancy a first
+                              // repeat pass stores for the second (words 0-3 go to
+                              // cand_shape)
     uint32_t* small_hash;     // [2]: D4 hash of the monomer and of the domino
     jatam_result_t* records;  // [max_n] records of a GA generation
 };
