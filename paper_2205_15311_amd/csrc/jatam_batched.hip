@@ -1482,27 +1482,28 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
         end(kStageSort + kStagesPerClass * k);
         // the bond table holds colours 0..7
         const bool table = a.c <= 8;
-        if (launch[k].repeat_mapping != 1) {
-            // the proof and the first (mapping 2) or only (mapping 0) repeat
-            // pass in one kernel on the repeat grid; with two passes the
-            // undecided candidates go to the staging array (free after the
-            // sort) for the second, which in the 16 x 16 layout makes only
-            // runs kRepeatFirstRuns .. R-1 (the 32 x 32 layout remakes all)
-            const bool two = launch[k].repeat_mapping == 2 && a.runs > kRepeatFirstRuns;
+        const int mapping = launch[k].repeat_mapping;
+        if (mapping == 2 && a.runs > kRepeatFirstRuns) {
+            // two passes: the proof and the first pass (runs 0 ..
+            // kRepeatFirstRuns-1, a cheap round of 16 candidates per wave)
+            // in one kernel on the repeat grid, the undecided candidates to
+            // the staging array (free after the sort) for the second pass,
+            // which in the 16 x 16 layout makes only runs kRepeatFirstRuns ..
+            // R-1 (the 32 x 32 layout remakes all)
             uint32_t* q1 = a.ws.cand_idx[k];
             uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;   // cleared by the size sort
             begin(kStageProve + kStagesPerClass * k);
-            launch_prove_repeat<TM>(a, k, table, rb, two ? kRepeatFirstRuns : a.runs, q1, c1,
-                                    stream);
+            launch_prove_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, q1, c1, stream);
             end(kStageProve + kStagesPerClass * k);
             begin(kStageRepeat + kStagesPerClass * k);
-            if (two)
-                launch_repeat<TM>(a, k, table, rb, a.runs, k == 0 ? kRepeatFirstRuns : 0, false,
-                                  q1, c1, nullptr, nullptr, stream);
+            launch_repeat<TM>(a, k, table, rb, a.runs, k == 0 ? kRepeatFirstRuns : 0, false, q1, c1,
+                              nullptr, nullptr, stream);
             end(kStageRepeat + kStagesPerClass * k);
         } else {
-            // forced shapes are final; the rest are compacted for the
-            // one-lane-per-candidate repeat runs
+            // forced shapes are final; the rest are compacted, in queue
+            // order, for one pass of all R runs per candidate (mapping 0: a
+            // round of 64 / R candidates is too costly to interleave with the
+            // proof) or the one-lane-per-candidate repeat runs (mapping 1)
             begin(kStageProve + kStagesPerClass * k);
             if (k == 0)
                 hipLaunchKernelGGL((prove_kernel<16, TM>), dim3(nb), dim3(64), 0, stream, a, 0);
@@ -1516,7 +1517,10 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             hipLaunchKernelGGL(compact_kernel, dim3(nb), dim3(256), 0, stream, a, k);
             end(kStageProve + kStagesPerClass * k);
             begin(kStageRepeat + kStagesPerClass * k);
-            if (k == 0 && table)
+            if (mapping != 1)
+                launch_repeat<TM>(a, k, table, rb, a.runs, 0, false, a.ws.sorted[k],
+                                  a.ws.counters + kCntCand + k, nullptr, nullptr, stream);
+            else if (k == 0 && table)
                 hipLaunchKernelGGL((repeat_seq_kernel<16, TM, true>), dim3(rb), dim3(64), 0, stream,
                                    a, 0);
             else if (k == 0)
