@@ -33,12 +33,12 @@
 //                 run 0's) is found in LDS, and for DET genotypes the 8
 //                 orientation hashes are split across the group's lanes.
 //                 By default in two passes (runs 0-3, then the rest for the
-//                 candidates without a witness); the proof and the first
-//                 pass share one kernel (prove_repeat), each wave running
-//                 the repeat rounds of the candidates it failed to prove.
-//                 Or (repeat_seq) one lane per candidate making its runs in
-//                 turn and stopping at the first witness, after a separate
-//                 proof and compaction.
+//                 candidates without a witness); then the proof and the
+//                 first pass share one kernel (prove_repeat), each wave
+//                 running the repeat rounds of the candidates it failed to
+//                 prove.  Or in one pass, or (repeat_seq) one lane per
+//                 candidate making its runs in turn and stopping at the
+//                 first witness, both after a separate proof and compaction.
 //
 // Global atomics on shared counters are rare: the first-run claim counter,
 // taken a few chunks at a time by waves that have finished their dealt-out
