@@ -278,6 +278,25 @@ struct DrawPair {
     }
 };
 
+// A DrawPair whose caller runs prefetch_draws before every step: the block
+// of the next draw is then always present, so draw() reads it without the
+// fallback computation (and the step loop holds one copy of the generator).
+struct PrefetchedDraws {
+    DrawPair& dp;
+    __device__ __forceinline__ uint32_t draw(uint32_t s, int, uint32_t, uint32_t, uint32_t,
+                                             uint32_t) const
+    {
+        const uint32_t blk = s >> 2;
+        const bool odd = (blk & 1u) != 0;
+        const uint32_t k = s & 3u;
+        const uint32_t x0 = DrawPair::pick(odd, dp.o0, dp.e0), x1 = DrawPair::pick(odd, dp.o1, dp.e1);
+        const uint32_t x2 = DrawPair::pick(odd, dp.o2, dp.e2), x3 = DrawPair::pick(odd, dp.o3, dp.e3);
+        const uint32_t lo = DrawPair::pick((k & 1u) != 0, x1, x0);
+        const uint32_t hi = DrawPair::pick((k & 1u) != 0, x3, x2);
+        return DrawPair::pick((k & 2u) != 0, hi, lo);
+    }
+};
+
 // Wave-wide Philox fill for lanes that keep a DrawPair: when the next draw
 // of any stepping lane lacks its block, every stepping lane computes the
 // block it lacks, so one pass of the generator serves the whole wave.  Call

@@ -475,9 +475,13 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 break;
             prefetch_draws(dc, stepping, st, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
                            (uint32_t)(gd.rng_id >> 32));
-            if (stepping)
-                ev = run_step(m, g, st, dc, gd.grid, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
+            if (stepping) {
+                // prefetch_draws above made the block of every stepping
+                // lane's next draw present
+                PrefetchedDraws pd{dc};
+                ev = run_step(m, g, st, pd, gd.grid, 0, a.key0, a.key1, (uint32_t)gd.rng_id,
                               (uint32_t)(gd.rng_id >> 32));
+            }
             const uint64_t waiting = __ballot(!busy || run_over(ev, st, gd.grid));
             if ((uint32_t)__popcll(waiting) >= enough)
                 break;

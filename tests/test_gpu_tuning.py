@@ -256,7 +256,7 @@ def test_repeat_mappings_keep_the_golden_records(jt, mapping, runs):
     assert tally.cpu().tolist() == want
 
 
-@pytest.mark.parametrize("runs", [1, 2, 4, 5, 7, 33, 64])
+@pytest.mark.parametrize("runs", [1, 2, 4, 5, 7, 8, 12, 20, 33, 64])
 def test_two_pass_repeat_at_every_run_count(jt, runs):
     """Two repeat passes at run counts below, at and above the first pass's
     4 runs, on S_{2,8} and three-tile genotypes: the oracle's records."""
