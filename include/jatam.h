@@ -257,8 +257,10 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *                 first witness, a lane that finishes taking the next
  *                 candidate from the queue; 2 makes two passes, the first
  *                 with 4 lanes per candidate (runs 0..3: a witness among
- *                 them decides), the second with R lanes for the
- *                 candidates the first left undecided.
+ *                 them decides, in the same kernel as the forced-shape
+ *                 proof), the second for the candidates the first left
+ *                 undecided (G <= 16: R - 4 lanes making runs 4..R-1;
+ *                 above: R lanes).
  */
 typedef struct {
     int refill;
@@ -371,6 +373,9 @@ int jatam_batch_autotune_log(const jatam_batch_t* batch, int i, jatam_tuning_t* 
  * calls[s]; it returns the number of stages written.  Stage names:
  * jatam_batch_stage_name (0 first runs, 1 size sort, 2 forced-shape proof
  * and compaction, 3 repeat runs for G <= 16; 4-7 the same for G <= 32).
+ * With two repeat passes (repeat_mapping 2 and runs > 4) stage 2 is the
+ * proof together with the first repeat pass (one kernel) and stage 3 the
+ * second pass.
  */
 int jatam_batch_set_timing(jatam_batch_t* batch, int enable);
 int jatam_batch_stage_times(jatam_batch_t* batch, double* ms, int* calls, int max_stages);
