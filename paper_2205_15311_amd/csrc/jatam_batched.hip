@@ -1307,29 +1307,40 @@ int batch_init_small_hash(uint32_t* small_hash, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? JATAM_OK : JATAM_E_HIP;
 }
 
+// One-wave workgroups of `kernel` that are resident on a CU at once.  The
+// runtime's answer is capped by the CU's LDS as it is handed out on gfx950:
+// in granules of 1,280 bytes, 128 per CU.  (Measured with spinning
+// workgroups of a given dynamic LDS size: eleven of 14,080 bytes run
+// together, eleven of 14,336 do not, nor ten of 15,744, while four of
+// 39,680 and three of 52,480 do; the runtime reports eleven, eleven and ten
+// for the first three.  A persistent grid sized above the true count leaves
+// its last workgroups waiting for the first ones to finish.)
+template <class K>
+static int resident_per_cu(K kernel)
+{
+    constexpr size_t kLdsGranule = 1280, kLdsGranules = 128;
+    int occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kernel)) == hipSuccess &&
+        attr.sharedSizeBytes > 0) {
+        const size_t granules = (attr.sharedSizeBytes + kLdsGranule - 1) / kLdsGranule;
+        const int fit = (int)(kLdsGranules / granules);
+        occ = fit < occ ? (fit < 1 ? 1 : fit) : occ;
+    }
+    return occ;
+}
+
 template <int W, int TM>
 static void occupancy_of(int out[3])
 {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[0], first_run_kernel<W, TM, kInRange>,
-                                                     64, 0) !=
-            hipSuccess ||
-        out[0] < 1)
-        out[0] = 1;
+    out[0] = resident_per_cu(first_run_kernel<W, TM, kInRange>);
     // the repeat grid runs the proof + first pass kernel and the second pass
-    int fused = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[1], repeat_kernel<W, TM, true>, 64, 0) !=
-            hipSuccess ||
-        out[1] < 1)
-        out[1] = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fused, prove_repeat_kernel<W, TM, true>, 64,
-                                                     0) != hipSuccess ||
-        fused < 1)
-        fused = 1;
-    out[1] = out[1] < fused ? out[1] : fused;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&out[2], repeat_seq_kernel<W, TM, true>, 64,
-                                                     0) != hipSuccess ||
-        out[2] < 1)
-        out[2] = 1;
+    const int repeat = resident_per_cu(repeat_kernel<W, TM, true>);
+    const int fused = resident_per_cu(prove_repeat_kernel<W, TM, true>);
+    out[1] = repeat < fused ? repeat : fused;
+    out[2] = resident_per_cu(repeat_seq_kernel<W, TM, true>);
 }
 
 void batch_occupancy(int occ[2][2][3])
