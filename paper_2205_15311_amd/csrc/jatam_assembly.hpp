@@ -123,27 +123,45 @@ __device__ __forceinline__ void frontier_group_add(RunState& st, int q, bool add
 //
 // `added`, if given, receives bit d for every direction d whose site joined
 // the frontier (the movelist traversal pushes those sites).
-template <int W, int B, class Src>
-__device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
-                                           int G, int p, uint32_t tuple,
-                                           uint32_t* added = nullptr)
+//
+// The check only looks at the neighbours' own bits and nibbles, so the
+// words holding them may be read before p itself is marked (NeighbourWords,
+// read by the step together with p's pending word).
+struct NeighbourWords {
+    int q[4];                          // the cells N, E, S, W of p
+    uint32_t ow[4], fw[4], pw[4];      // their occupancy, frontier, pending words
+};
+
+template <int W, int B>
+__device__ __forceinline__ NeighbourWords read_neighbours(LaneGrid<W, B>& g, int p)
 {
     constexpr int kMask = W * W - 1;
-    uint32_t ow[4], fw[4], pw[4];
-    SiteOpts opt[4];
-    int q[4];
+    NeighbourWords nw;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int delta = d == 0 ? -W : d == 1 ? 1 : d == 2 ? W : -1;
-        q[d] = (p + delta) & kMask;
-        opt[d] = m.options_split(tuple, d);
+        nw.q[d] = (p + delta) & kMask;
+        nw.ow[d] = g.occ(nw.q[d] >> 5);
+        nw.fw[d] = g.fr(nw.q[d] >> 5);
+        nw.pw[d] = g.pend_word(nw.q[d]);
     }
+    return nw;
+}
+
+template <int W, int B, class Src>
+__device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
+                                           int G, int p, uint32_t tuple,
+                                           const NeighbourWords& nw,
+                                           uint32_t* added = nullptr)
+{
+    const int* const q = nw.q;
+    const uint32_t* const ow = nw.ow;
+    const uint32_t* const fw = nw.fw;
+    const uint32_t* const pw = nw.pw;
+    SiteOpts opt[4];
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        ow[d] = g.occ(q[d] >> 5);
-        fw[d] = g.fr(q[d] >> 5);
-        pw[d] = g.pend_word(q[d]);
-    }
+    for (int d = 0; d < 4; ++d)
+        opt[d] = m.options_split(tuple, d);
     // p lies in the box ([0, G-2]^2), so a neighbour is on the ring exactly
     // when p is on the box's edge in that direction (N and W wrap round the
     // torus onto row or column W-1)
@@ -176,6 +194,14 @@ __device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunS
         }
     }
     return unbound ? kEvUnbound : ambiguous ? kEvAmbig : kEvNone;
+}
+
+template <int W, int B, class Src>
+__device__ __forceinline__ int update_site(const Src& m, LaneGrid<W, B>& g, RunState& st,
+                                           int G, int p, uint32_t tuple,
+                                           uint32_t* added = nullptr)
+{
+    return update_site(m, g, st, G, p, tuple, read_neighbours(g, p), added);
 }
 
 // Philox block cache of a run: the 4 words of counter block `block`.  Kept
@@ -487,6 +513,11 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
         rest &= rest - 1u;
     const int bit = __builtin_ctz(rest);
     const int p = (w << 5) | bit;
+    // p's pending word and its neighbours' words in one round of LDS reads,
+    // issued before p leaves the frontier and is marked occupied (the
+    // neighbour check does not look at p's bits)
+    const uint32_t pw = g.pend_word(p);
+    const NeighbourWords nw = read_neighbours(g, p);
     fw &= ~(1u << bit);
     g.fr(w) = fw;
     if (fw == 0)
@@ -495,14 +526,13 @@ __device__ __forceinline__ int run_step(const Src& m, LaneGrid<W, B>& g, RunStat
     frontier_group_add<W>(st, p, false);
 
     // place the pending tile (its nibble stays: the cell keeps its tile)
-    const uint32_t pw = g.pend_word(p);
     const uint32_t sh = ((uint32_t)p & 7u) * 4u;
     const uint32_t tuple = m.oriented((int)((pw >> sh) & 15u));
     LaneGrid<W, B>::set_bits(g.occ(w), 1u << bit);
     st.osum |= 1u << w;
     st.size += 1;
     st.steps += 1;
-    return update_site(m, g, st, G, p, tuple);
+    return update_site(m, g, st, G, p, tuple, nw);
 }
 
 // One run from the seed to completion or to an event.
