@@ -1296,6 +1296,8 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
     const size_t staging = staging_entries(n, mb);
     DeviceWorkspace w;
     w.counters = (uint32_t*)take(kCntWords * sizeof(uint32_t));
+    w.queue_claim =
+        (uint32_t*)take(2 * kQueueClaimers * kQueueClaimStride * sizeof(uint32_t));
     w.small_hash = (uint32_t*)take(2 * sizeof(uint32_t));
     w.records = records ? (jatam_result_t*)take(n * sizeof(jatam_result_t)) : nullptr;
     for (int k = 0; k < 2; ++k) {

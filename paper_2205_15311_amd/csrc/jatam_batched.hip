@@ -35,16 +35,19 @@
 //                 By default in two passes (runs 0-3, then the rest for the
 //                 candidates without a witness); then the proof and the
 //                 first pass share one kernel (prove_repeat), each wave
+//                 claiming chunks of the sorted queue one at a time and
 //                 running the repeat rounds of the candidates it failed to
 //                 prove.  Or in one pass, or (repeat_seq) one lane per
 //                 candidate making its runs in turn and stopping at the
 //                 first witness, both after a separate proof and compaction.
 //
-// Global atomics on shared counters are rare: the first-run claim counter,
+// Global atomics on shared counters are few: the first-run claim counter,
 // taken a few chunks at a time by waves that have finished their dealt-out
-// share (same-address atomics serialise across the 8 XCDs), and the second
-// repeat queue's counter, one atomic per wave and round of the first pass;
-// every other queue is a per-wave segment or a scan.  Records are identical
+// share (same-address atomics serialise across the 8 XCDs); the fused
+// kernel's chunk claims, one atomic per chunk spread over eight counters in
+// separate 256-byte blocks; and the second repeat queue's counter, one
+// atomic per wave and round of the first pass.  Every other queue is a
+// per-wave segment or a scan.  Records are identical
 // to the plain kernel's: each is a pure function of the genotype, never of
 // the schedule.
 #include "jatam_assembly.hpp"
@@ -512,6 +515,8 @@ __global__ __launch_bounds__(256) void sort_hist_kernel(BatchArgs a, int klass)
     __syncthreads();
     if (seg == 0 && threadIdx.x == 0)
         a.ws.counters[kCntRepeat2 + klass] = 0;   // the second repeat queue, empty
+    if (seg == 0 && threadIdx.x < kQueueClaimers)   // the fused kernel's chunk claims
+        a.ws.queue_claim[(klass * kQueueClaimers + threadIdx.x) * kQueueClaimStride] = 0;
     const uint32_t n = a.ws.seg_count[klass][seg];
     const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256)
@@ -1116,7 +1121,22 @@ __global__ __launch_bounds__(64) void prove_repeat_kernel(const BatchArgs a, int
         wave_lds_sync();
         npend = rest;
     };
-    for (uint32_t c = blockIdx.x; c < qchunks; c += gridDim.x) {
+    // Chunks are claimed one at a time, so that waves end together however
+    // the proofs and rounds of their chunks differ: counter x (x = the
+    // block's index mod 8, its XCD under the round-robin dispatch of
+    // workgroups) hands out chunks x, x + 8, x + 16, ... of the queue, so
+    // each counter serves an even share of every part of the size-sorted
+    // queue.  The counters are cleared by the size sort.
+    const uint32_t claimer = blockIdx.x % (uint32_t)kQueueClaimers;
+    uint32_t* const claim_ctr =
+        a.ws.queue_claim + (klass * kQueueClaimers + claimer) * kQueueClaimStride;
+    auto claim = [&]() -> uint32_t {
+        uint32_t q = 0;
+        if (lane == 0)
+            q = atomicAdd(claim_ctr, 1u);
+        return claimer + (uint32_t)kQueueClaimers * (uint32_t)__shfl((int)q, 0);
+    };
+    for (uint32_t c = claim(); c < qchunks; c = claim()) {
         const uint32_t pos = c * 64 + lane;
         uint32_t idx;
         const bool kept = prove_one<W, TM>(a, rw.first, rw.out, lg, st, cache, tally, klass,

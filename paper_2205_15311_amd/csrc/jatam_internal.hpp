@@ -43,6 +43,11 @@ constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
 constexpr int kMaxClaimChunks = 8;  // most 64-item chunks one first-run claim may take
 constexpr int kRepeatFirstRuns = 4; // runs per candidate in the first of two repeat passes
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
+// Chunk claims of the fused proof + first repeat pass kernel: one counter per
+// XCD, each in a 256-byte block of its own (counters that share a block
+// serialise their atomics), per grid class.
+constexpr int kQueueClaimers = 8;
+constexpr int kQueueClaimStride = 64;   // words between two counters
 constexpr int kMaxScanBlocks = 1024;
 
 // Entries of the candidate staging arrays for calls of up to max_n items on
@@ -59,6 +64,8 @@ inline size_t staging_entries(size_t max_n, size_t max_blocks)
 // persistent grid of at most max_blocks one-wave blocks.
 struct DeviceWorkspace {
     uint32_t* counters;       // kCntWords
+    uint32_t* queue_claim;    // [2 * kQueueClaimers * kQueueClaimStride]: counter x
+                              // of class k at word (k * kQueueClaimers + x) * stride
     uint32_t* seg_count[2];   // [max_blocks] candidates staged by each wave
     uint32_t* seg_hist[2];    // [kSizeBuckets * max_blocks] bucket-major counts
     uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
