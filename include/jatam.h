@@ -239,10 +239,12 @@ int jatam_batch_set_refill(jatam_batch_t* batch, int idle_lanes);
  *                 of at least 2^20 genotypes and 1 below.  The G <= 16
  *                 class at 1 turns the window off.
  *   claim_share   first runs: sixteenths of the input's 64-item chunks that
- *                 waves claim from a device counter, up to four chunks at a
- *                 time (fewer when each wave gets few chunks; none when
+ *                 waves claim from device counters (eight, each for a
+ *                 contiguous eighth of the claimed chunks; a wave moves to
+ *                 the next counter when its own runs dry), up to four chunks
+ *                 at a time (fewer when each wave gets few chunks; none when
  *                 each wave gets under 16, where all are dealt out),
- *                 once their dealt-out chunks are done (0..16; default 8).
+ *                 once their dealt-out chunks are done (0..16; default 12).
  *                 The rest are dealt out in turn (chunk k to wave k mod the
  *                 grid).  Run lengths follow the genome's digits, so dealt-
  *                 out chunks leave some waves far more work than others;

@@ -1263,7 +1263,7 @@ namespace jatam {
 // 1, 2 or 3); class 1 in one (large deterministic shapes need every run).
 jatam_tuning_t default_tuning(int klass)
 {
-    return jatam_tuning_t{24, 64, 64, 0, 8, 4, klass == 0 ? 2 : 0};
+    return jatam_tuning_t{24, 64, 64, 0, 12, 4, klass == 0 ? 2 : 0};
 }
 
 int max_first_blocks(const int occ[2][2][3], int cus)
@@ -1296,8 +1296,8 @@ size_t carve_workspace(uint8_t* base, size_t max_n, int max_blocks, bool records
     const size_t staging = staging_entries(n, mb);
     DeviceWorkspace w;
     w.counters = (uint32_t*)take(kCntWords * sizeof(uint32_t));
-    w.queue_claim =
-        (uint32_t*)take(2 * kQueueClaimers * kQueueClaimStride * sizeof(uint32_t));
+    w.run_claim = (uint32_t*)take(2 * kClaimCounters * kClaimStride * sizeof(uint32_t));
+    w.queue_claim = (uint32_t*)take(2 * kClaimCounters * kClaimStride * sizeof(uint32_t));
     w.small_hash = (uint32_t*)take(2 * sizeof(uint32_t));
     w.records = records ? (jatam_result_t*)take(n * sizeof(jatam_result_t)) : nullptr;
     for (int k = 0; k < 2; ++k) {

@@ -7,7 +7,7 @@
 //
 //   first_run<W>  persistent waves over 64-genotype input chunks: a share of
 //                 the chunks is dealt out (chunk k to wave k mod the grid),
-//                 the rest are claimed a few at a time from a device counter
+//                 the rest are claimed a few at a time from device counters
 //                 by the waves that run out of work first.  A wave screens a
 //                 chunk (decode, bond options of the seed: an ambiguous seed
 //                 neighbour is ND_SITE, a seed with nothing to bond is a DET
@@ -41,13 +41,13 @@
 //                 candidate making its runs in turn and stopping at the
 //                 first witness, both after a separate proof and compaction.
 //
-// Global atomics on shared counters are few: the first-run claim counter,
-// taken a few chunks at a time by waves that have finished their dealt-out
-// share (same-address atomics serialise across the 8 XCDs); the fused
-// kernel's chunk claims, one atomic per chunk spread over eight counters in
-// separate 256-byte blocks; and the second repeat queue's counter, one
-// atomic per wave and round of the first pass.  Every other queue is a
-// per-wave segment or a scan.  Records are identical
+// Global atomics on shared counters are few: the first-run claims, a few
+// chunks at a time by waves that have finished their dealt-out share, and
+// the fused kernel's chunk claims, one atomic per chunk, each spread over
+// eight counters in separate 256-byte blocks (atomics on one address from
+// every wave serialise); and the second repeat queue's counter, one atomic
+// per wave and round of the first pass.  Every other queue is a per-wave
+// segment or a scan.  Records are identical
 // to the plain kernel's: each is a pure function of the genotype, never of
 // the schedule.
 #include "jatam_assembly.hpp"
@@ -282,12 +282,17 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     const uint32_t n_items = a.n_dev != nullptr ? *a.n_dev : (uint32_t)a.n;
     const uint32_t nchunks = (n_items + 63) / 64;
     // Chunks below static_end are dealt out: this wave owns wave + k*nwaves.
-    // The rest are claimed a few at a time from a device counter by
-    // the waves that run out of work first, which evens out the waves' end
-    // times.  A claim is made only while the wave's candidate segment can
-    // hold every item it has in flight plus the claim (a wave that cannot
-    // claim with nothing in flight has staged more than its dealt share of
-    // slots, so not all waves can be in that state while chunks are left).
+    // The rest are claimed a few at a time by the waves that run out of
+    // work first, which evens out the waves' end times.  They are split
+    // into eight contiguous parts with a counter each (one atomic per claim
+    // on one address from every wave serialises): a wave starts at part
+    // (wave mod 8), its XCD's under the round-robin dispatch of workgroups,
+    // and moves on to the next part when one runs dry, so the parts even
+    // out among themselves too.  A claim is made only while the wave's
+    // candidate segment can hold every item it has in flight plus the claim
+    // (a wave that cannot claim with nothing in flight has staged more than
+    // its dealt share of slots, so not all waves can be in that state while
+    // chunks are left; any wave can take any part's chunks).
     // Claims are made only where every wave gets at least 16 chunks (with a
     // chunk or two per wave there is nothing to even out), of up to
     // claim_chunks chunks, fewer while a large claim would leave most waves
@@ -301,7 +306,11 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     uint32_t next_chunk = wave;
     uint32_t claim_next = 0, claim_end = 0;   // chunks claimed, not yet screened
     bool claims_left = static_end < nchunks;
-    uint32_t* const claim_ctr = a.ws.counters + kCntClaim + klass;
+    const uint32_t claim_blocks =
+        claim_size == 0 ? 0u : (nchunks - static_end + claim_size - 1) / claim_size;
+    const uint32_t part_blocks = (claim_blocks + kClaimCounters - 1) / kClaimCounters;
+    uint32_t* const claim_ctr = a.ws.run_claim + klass * kClaimCounters * kClaimStride;
+    uint32_t part = wave % (uint32_t)kClaimCounters, parts_dry = 0;
     uint32_t head = 0, queued = 0;            // survivor ring (wave-uniform)
     uint32_t staged = 0;                      // candidates in this wave's segment
     uint32_t* seg_idx = a.ws.cand_idx[klass] + (size_t)wave * a.seg_cap;
@@ -376,10 +385,19 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                             starved = true;
                             break;
                         }
-                        uint32_t base = 0;
-                        if (lane_id() == 0)
-                            base = atomicAdd(claim_ctr, claim_size);
-                        base = static_end + (uint32_t)__shfl((int)base, 0);
+                        uint32_t base = nchunks;
+                        while (parts_dry < (uint32_t)kClaimCounters) {
+                            uint32_t q = 0;
+                            if (lane_id() == 0)
+                                q = atomicAdd(claim_ctr + part * kClaimStride, 1u);
+                            const uint32_t blk = part * part_blocks + (uint32_t)__shfl((int)q, 0);
+                            if (blk < min((part + 1u) * part_blocks, claim_blocks)) {
+                                base = static_end + blk * claim_size;
+                                break;
+                            }
+                            part = (part + 1u) % (uint32_t)kClaimCounters;
+                            ++parts_dry;
+                        }
                         if (base >= nchunks) {
                             claims_left = false;
                             starved = true;
@@ -515,8 +533,8 @@ __global__ __launch_bounds__(256) void sort_hist_kernel(BatchArgs a, int klass)
     __syncthreads();
     if (seg == 0 && threadIdx.x == 0)
         a.ws.counters[kCntRepeat2 + klass] = 0;   // the second repeat queue, empty
-    if (seg == 0 && threadIdx.x < kQueueClaimers)   // the fused kernel's chunk claims
-        a.ws.queue_claim[(klass * kQueueClaimers + threadIdx.x) * kQueueClaimStride] = 0;
+    if (seg == 0 && threadIdx.x < kClaimCounters)   // the fused kernel's chunk claims
+        a.ws.queue_claim[(klass * kClaimCounters + threadIdx.x) * kClaimStride] = 0;
     const uint32_t n = a.ws.seg_count[klass][seg];
     const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
     for (uint32_t i = threadIdx.x; i < n; i += 256)
@@ -1127,14 +1145,14 @@ __global__ __launch_bounds__(64) void prove_repeat_kernel(const BatchArgs a, int
     // workgroups) hands out chunks x, x + 8, x + 16, ... of the queue, so
     // each counter serves an even share of every part of the size-sorted
     // queue.  The counters are cleared by the size sort.
-    const uint32_t claimer = blockIdx.x % (uint32_t)kQueueClaimers;
+    const uint32_t claimer = blockIdx.x % (uint32_t)kClaimCounters;
     uint32_t* const claim_ctr =
-        a.ws.queue_claim + (klass * kQueueClaimers + claimer) * kQueueClaimStride;
+        a.ws.queue_claim + (klass * kClaimCounters + claimer) * kClaimStride;
     auto claim = [&]() -> uint32_t {
         uint32_t q = 0;
         if (lane == 0)
             q = atomicAdd(claim_ctr, 1u);
-        return claimer + (uint32_t)kQueueClaimers * (uint32_t)__shfl((int)q, 0);
+        return claimer + (uint32_t)kClaimCounters * (uint32_t)__shfl((int)q, 0);
     };
     for (uint32_t c = claim(); c < qchunks; c = claim()) {
         const uint32_t pos = c * 64 + lane;
@@ -1399,10 +1417,11 @@ int launch_records_differ(const jatam_result_t* x, const jatam_result_t* y, uint
 }
 
 // Zeroes one counter word (a kernel rather than a memset: graph-safe).
-__global__ void clear_word_kernel(uint32_t* w)
+// Clears the claim counters of one grid class (before its first-run kernel).
+__global__ void clear_claims_kernel(uint32_t* ctr)
 {
-    if (threadIdx.x == 0)
-        *w = 0u;
+    if (threadIdx.x < kClaimCounters)
+        ctr[threadIdx.x * kClaimStride] = 0u;
 }
 
 // The first-run kernel compiled for the call's input mode.
@@ -1502,8 +1521,8 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             a.narrow_max = 16;
         }
         if (a.dyn16 > 0)
-            hipLaunchKernelGGL(clear_word_kernel, dim3(1), dim3(64), 0, stream,
-                               a.ws.counters + kCntClaim + k);
+            hipLaunchKernelGGL(clear_claims_kernel, dim3(1), dim3(64), 0, stream,
+                               a.ws.run_claim + k * kClaimCounters * kClaimStride);
         if (k == 0)
             launch_first<16, TM>(a, nb, stream, 0);
         else

@@ -35,7 +35,6 @@ enum {
     kCntSlice = 3,    // slice counter of a graph-replayed enumeration
     kCntCandAll = 4,  // [2] candidates before the forced-shape proof
     kCntOverflow = 6, // items that left the 16 x 16 window (rerun in 32 x 32 grids)
-    kCntClaim = 7,    // [2] chunks claimed past the static share (first-run stage)
     kCntRepeat2 = 9,  // [2] candidates left for the second repeat pass
     kCntWords = 16,
 };
@@ -43,11 +42,12 @@ constexpr int kSizeBuckets = 64;    // run-0 size buckets of the repeat queue
 constexpr int kMaxClaimChunks = 8;  // most 64-item chunks one first-run claim may take
 constexpr int kRepeatFirstRuns = 4; // runs per candidate in the first of two repeat passes
 constexpr int kScanBlock = 1024;    // histogram entries per block of the size scan
-// Chunk claims of the fused proof + first repeat pass kernel: one counter per
-// XCD, each in a 256-byte block of its own (counters that share a block
-// serialise their atomics), per grid class.
-constexpr int kQueueClaimers = 8;
-constexpr int kQueueClaimStride = 64;   // words between two counters
+// Chunk claims of the first-run kernel and of the fused proof + first repeat
+// pass kernel: eight counters per grid class and stage (one per XCD), each
+// in a 256-byte block of its own (counters that share a block serialise
+// their atomics).
+constexpr int kClaimCounters = 8;
+constexpr int kClaimStride = 64;   // words between two counters
 constexpr int kMaxScanBlocks = 1024;
 
 // Entries of the candidate staging arrays for calls of up to max_n items on
@@ -64,8 +64,9 @@ inline size_t staging_entries(size_t max_n, size_t max_blocks)
 // persistent grid of at most max_blocks one-wave blocks.
 struct DeviceWorkspace {
     uint32_t* counters;       // kCntWords
-    uint32_t* queue_claim;    // [2 * kQueueClaimers * kQueueClaimStride]: counter x
-                              // of class k at word (k * kQueueClaimers + x) * stride
+    uint32_t* run_claim;      // [2 * kClaimCounters * kClaimStride]: first-run claim
+                              // counter x of class k at word (k * 8 + x) * kClaimStride
+    uint32_t* queue_claim;    // the same for the fused proof kernel's queue chunks
     uint32_t* seg_count[2];   // [max_blocks] candidates staged by each wave
     uint32_t* seg_hist[2];    // [kSizeBuckets * max_blocks] bucket-major counts
     uint32_t* scan_sums[2];   // [kMaxScanBlocks] block totals of the histogram scan
@@ -107,8 +108,8 @@ struct BatchArgs {
     const uint32_t* n_dev;          // nullptr, or the item count on the device
                                     // (first-run stage; at most n)
     int refill;                     // idle lanes that trigger a refill (1..64, per class)
-    int dyn16;                      // sixteenths of the first-run chunks claimed from a
-                                    // device counter rather than dealt out (0..16)
+    int dyn16;                      // sixteenths of the first-run chunks claimed from
+                                    // device counters rather than dealt out (0..16)
     int claim_chunks;               // most chunks one claim takes (1..kMaxClaimChunks)
     uint32_t seg_cap;               // staging slots per wave (set per launch)
     uint32_t small0, small1;        // D4 hashes of the monomer and the domino (the
