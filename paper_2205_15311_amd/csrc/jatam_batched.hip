@@ -22,8 +22,9 @@
 //   size sort     a counting sort of the candidates by run-0 size, largest
 //                 first (all runs of a deterministic genotype have that size,
 //                 so this orders the later work by its exact cost): per
-//                 segment histograms in LDS, one scan, scatter with LDS
-//                 cursors that moves each packed shape beside its candidate.
+//                 segment histograms counted in LDS by the first-run waves
+//                 as they stage, one scan, scatter with LDS cursors that
+//                 moves each packed shape beside its candidate.
 //   prove<W>      one lane per candidate checks whether its run-0 shape is
 //                 guarded (every growth order ends in it), from the packed
 //                 shape or, where the shape did not pack, a replay: then the
@@ -258,6 +259,14 @@ __device__ __forceinline__ uint32_t packed_hash(uint64_t key, uint32_t small0, u
 // ---------------------------------------------------------------------------
 constexpr int kRing = 128;   // LDS survivor ring per wave (>= 2 chunks)
 
+// Size-sort bucket of a run-0 size: 64 buckets, exact up to 47 cells, then
+// 64 cells wide; the largest sizes get the smallest keys.
+__device__ __forceinline__ uint32_t size_key(uint32_t size)
+{
+    const uint32_t b = size < 48 ? size : 48 + min(15u, (size - 48) >> 6);
+    return kSizeBuckets - 1 - b;
+}
+
 template <int W, int TM, int kIn>
 __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int klass)
 {
@@ -269,16 +278,27 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     __shared__ uint32_t ring[kRing];       // survivor indices
     __shared__ uint32_t ring_opt[kRing];   // their seeds' four site codes
     __shared__ uint4 cache_mem[kShapeCache];
+    __shared__ uint32_t size_hist[kSizeBuckets];   // sizes this wave staged, by bucket
     LaneGrid<W, 64> g{smem + threadIdx.x};
     g.clear_all();
     WaveShapeCache cache{cache_mem};
     cache.clear(lane_id());
+    static_assert(kSizeBuckets == 64, "one bucket per lane");
+    size_hist[lane_id()] = 0;
     __syncthreads();
     RunState st{0, 0, 0, 0, 0, false};
     DrawPair dc;
     dc.reset();
 
     const uint32_t wave = blockIdx.x, nwaves = gridDim.x;
+    if (wave == 0) {
+        // counters of the later stages of this class (the previous call's
+        // kernels are done, and these are first used after the size sort)
+        if (lane_id() == 0)
+            a.ws.counters[kCntRepeat2 + klass] = 0;   // the second repeat queue, empty
+        if (lane_id() < kClaimCounters)               // the fused kernel's chunk claims
+            a.ws.queue_claim[(klass * kClaimCounters + lane_id()) * kClaimStride] = 0;
+    }
     const uint32_t n_items = a.n_dev != nullptr ? *a.n_dev : (uint32_t)a.n;
     const uint32_t nchunks = (n_items + 63) / 64;
     // Chunks below static_end are dealt out: this wave owns wave + k*nwaves.
@@ -365,6 +385,7 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
                 seg_size[pos] = (uint16_t)st.size;
                 // the shape, for the proof stage to check without a replay
                 seg_shape[pos] = pack_shape(g, gd.grid, st.size);
+                atomicAdd(&size_hist[size_key((uint32_t)st.size)], 1u);
             }
             staged += (uint32_t)__popcll(cm);
         }
@@ -510,39 +531,17 @@ __global__ __launch_bounds__(64) void first_run_kernel(const BatchArgs a, int kl
     }
     if (lane_id() == 0)
         a.ws.seg_count[klass][wave] = staged;
+    wave_lds_sync();   // every staged size counted
+    a.ws.seg_hist[klass][(uint32_t)lane_id() * nwaves + wave] = size_hist[lane_id()];
     tally.flush(a.tally);
 }
 
 // ---------------------------------------------------------------------------
 // Size sort: 64 buckets, exact up to 47 cells, then 64 cells wide; largest
-// first.
+// first.  Each first-run wave counts the sizes it stages (its segment's
+// histogram, stored bucket-major); the sort scans the histograms and
+// scatters.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t size_key(uint32_t size)
-{
-    const uint32_t b = size < 48 ? size : 48 + min(15u, (size - 48) >> 6);
-    return kSizeBuckets - 1 - b;
-}
-
-// One block per segment: its bucket histogram, stored bucket-major.
-__global__ __launch_bounds__(256) void sort_hist_kernel(BatchArgs a, int klass)
-{
-    __shared__ uint32_t hist[kSizeBuckets];
-    const uint32_t seg = blockIdx.x, nseg = gridDim.x;
-    if (threadIdx.x < kSizeBuckets)
-        hist[threadIdx.x] = 0;
-    __syncthreads();
-    if (seg == 0 && threadIdx.x == 0)
-        a.ws.counters[kCntRepeat2 + klass] = 0;   // the second repeat queue, empty
-    if (seg == 0 && threadIdx.x < kClaimCounters)   // the fused kernel's chunk claims
-        a.ws.queue_claim[(klass * kClaimCounters + threadIdx.x) * kClaimStride] = 0;
-    const uint32_t n = a.ws.seg_count[klass][seg];
-    const uint16_t* sz = a.ws.cand_size[klass] + (size_t)seg * a.seg_cap;
-    for (uint32_t i = threadIdx.x; i < n; i += 256)
-        atomicAdd(&hist[size_key(sz[i])], 1u);
-    __syncthreads();
-    if (threadIdx.x < kSizeBuckets)
-        a.ws.seg_hist[klass][threadIdx.x * nseg + seg] = hist[threadIdx.x];
-}
 
 // Exclusive scan of the bucket-major histogram in three coalesced passes:
 // each block scans kScanBlock entries in place and writes its total; one
@@ -1100,7 +1099,7 @@ __global__ __launch_bounds__(64) void repeat_kernel(const BatchArgs a, int klass
 // (RepeatWave::round).  The proof's steady integer work and the runs'
 // latency-bound steps share the CUs, and no compaction or launch sits
 // between them.  With rpass < R the candidates without a witness go to the
-// second queue (count_out, cleared by the size sort), in the 16 x 16 layout
+// second queue (count_out, cleared by the first-run kernel), in the 16 x 16 layout
 // with run 0's occupancy stored.
 // ---------------------------------------------------------------------------
 template <int W, int TM, bool kTable>
@@ -1144,7 +1143,7 @@ __global__ __launch_bounds__(64) void prove_repeat_kernel(const BatchArgs a, int
     // block's index mod 8, its XCD under the round-robin dispatch of
     // workgroups) hands out chunks x, x + 8, x + 16, ... of the queue, so
     // each counter serves an even share of every part of the size-sorted
-    // queue.  The counters are cleared by the size sort.
+    // queue.  The counters are cleared by the first-run kernel.
     const uint32_t claimer = blockIdx.x % (uint32_t)kClaimCounters;
     uint32_t* const claim_ctr =
         a.ws.queue_claim + (klass * kClaimCounters + claimer) * kClaimStride;
@@ -1529,7 +1528,6 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             launch_first<32, TM>(a, nb, stream, 1);
         end(kStageFirst + kStagesPerClass * k);
         begin(kStageSort + kStagesPerClass * k);
-        hipLaunchKernelGGL(sort_hist_kernel, dim3(nb), dim3(256), 0, stream, a, k);
         exclusive_scan(a.ws.seg_hist[k], (uint32_t)kSizeBuckets * nb, a.ws.scan_sums[k],
                        a.ws.counters + kCntCand + k, stream);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(nb), dim3(256), 0, stream, a, k);
@@ -1545,7 +1543,7 @@ static void launch_stages(BatchArgs a, const bool classes[2], const StageLaunch 
             // which in the 16 x 16 layout makes only runs kRepeatFirstRuns ..
             // R-1 (the 32 x 32 layout remakes all)
             uint32_t* q1 = a.ws.cand_idx[k];
-            uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;   // cleared by the size sort
+            uint32_t* c1 = a.ws.counters + kCntRepeat2 + k;   // cleared by the first runs
             begin(kStageProve + kStagesPerClass * k);
             launch_prove_repeat<TM>(a, k, table, rb, kRepeatFirstRuns, q1, c1, stream);
             end(kStageProve + kStagesPerClass * k);
