@@ -319,6 +319,37 @@ def test_staging_back_pressure_keeps_records(jt):
     assert tally.cpu().tolist() == [0, 0, 0, len(g)]
 
 
+def test_claim_parts_run_dry_unevenly(jt):
+    """First-run claims come from eight parts of the claimed chunks, one
+    counter each; a wave whose part runs dry moves on to the next.  Here the
+    last part holds only long runs and the others only genotypes the seed
+    decides, so most waves finish their own part early and take chunks of
+    the last one: every item is still classified exactly once."""
+    rng = np.random.default_rng(71)
+    pool = rng.integers(0, 1 << 24, size=1 << 17, dtype=np.uint64)
+    rec = ref.classify(pool, 2, grid=16, runs=20, seed=1)
+    # long run 0: an event after 40 or more placements, or a DET shape of 16
+    # or more cells; cheap: decided at the seed (no placement)
+    heavy = pool[((rec["cls"] != ref.DET) & (rec["steps"] >= 40))
+                 | ((rec["cls"] == ref.DET) & (rec["size"] >= 16))]
+    cheap = pool[rec["steps"] == 0]
+    assert len(heavy) > 500 and len(cheap) > 10000
+    n = 1 << 18
+    # 256 waves, 4,096 chunks: a quarter dealt out, 3,072 claimed one at a
+    # time in eight parts of 384 chunks; the last part is the list's last
+    # 384 * 64 entries
+    tail = 384 * 64
+    g = np.concatenate([np.resize(cheap, n - tail), np.resize(heavy, tail)])
+    want = ref.classify(g, 2, grid=16, runs=20, seed=1)
+    with jt.Batch(n) as b:
+        b.set_tuning(16, claim_share=12, claim_chunks=4, first_waves=1)
+        tally = torch.zeros(4, dtype=torch.int64, device="cuda")
+        got = records(b.classify(torch.from_numpy(g.view(np.int64)).cuda(), 2, 8, 16, 20, 1,
+                                 tally=tally))
+    assert_same(got, want, "uneven claim parts")
+    assert tally.cpu().tolist() == [int(np.sum(want["cls"] == k)) for k in range(4)]
+
+
 def test_autotune_cache_file(jt, tmp_path):
     """The tuning found for a key is written to the cache file and read back
     instead of searching again; another key adds a line; a broken line of a
